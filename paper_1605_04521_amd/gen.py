@@ -1,0 +1,307 @@
+"""Seeded synthetic inputs: meshes, permittivity maps, partitions and sources.
+
+This module produces problem *inputs* only (geometry, material data, the
+core partition and source descriptions).  It performs none of the method's
+arithmetic: no entity extraction, no basis functions, no assembly, no
+solves.  Both the library binding and the CPU reference take its output.
+
+Workload shapes follow the paper's imaging chamber (Sec. 1, Fig. 1: a
+metallic cylinder filled with a lossy matching medium, Sec. 5.1 for the
+medium values) and the unit-cube plane-wave problem used for validation.
+
+Time convention: fields vary as exp(-i w t), so a lossy medium has
+Im(eps) > 0.  The paper writes exp(+i w t) and Im(eps) < 0; every value
+here is the complex conjugate of the paper's.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BC_PEC = 0
+BC_IMPEDANCE = 1
+SRC_DIPOLE = 0
+SRC_PLANEWAVE = 1
+
+# speed of light (m/s); chamber wavenumber at 1 GHz in 1/m
+C0 = 299792458.0
+K0_1GHZ = 2.0 * math.pi * 1.0e9 / C0
+
+
+@dataclass
+class Mesh:
+    xyz: np.ndarray          # float64 [V,3]
+    tets: np.ndarray         # int32 [T,4]
+    bfaces: np.ndarray       # int32 [Fb,3], vertex ids ascending
+    bface_kind: np.ndarray   # int8 [Fb]
+    grid_n: int = 0          # cubes per side of the underlying Kuhn grid
+    cube_of_tet: np.ndarray = field(default=None, repr=False)  # int32 [T,3]
+
+
+@dataclass
+class Source:
+    kind: int
+    pos: tuple = (0.0, 0.0, 0.0)
+    pol: tuple = (0j, 0j, 0j)       # complex polarisation / dipole moment
+    dir: tuple = (0.0, 0.0, 0.0)    # plane-wave propagation direction
+
+
+@dataclass
+class Problem:
+    mesh: Mesh
+    eps: np.ndarray          # complex128 [T]
+    part: np.ndarray         # int32 [T]
+    n_sub: int
+    overlap: int
+    k0: float
+    degree: int
+    sources: list
+    name: str = ""
+
+
+# --------------------------------------------------------------------------
+# Kuhn-split structured grids
+# --------------------------------------------------------------------------
+
+_PERMS = list(itertools.permutations(range(3)))
+_UNIT = np.eye(3, dtype=np.int64)
+
+
+def _kuhn_topology(n: int):
+    """Vertex grid (n+1)^3 and the 6 Kuhn tets of each of the n^3 cubes.
+
+    Vertex (i,j,k) has id i + (n+1)(j + (n+1)k).  Cube (i,j,k) is split into
+    the tets {v, v+e_a, v+e_a+e_b, v+(1,1,1)} for each permutation (a,b,c)
+    of the axes, in itertools order.  Tet id = 6*(i + n(j + n k)) + perm.
+    """
+    m = n + 1
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    cube = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)   # i fastest
+    tets = np.empty((n ** 3, 6, 4), dtype=np.int64)
+    gidx = lambda p: p[:, 0] + m * (p[:, 1] + m * p[:, 2])
+    for q, (a, b, _) in enumerate(_PERMS):
+        p0 = cube
+        p1 = cube + _UNIT[a]
+        p2 = p1 + _UNIT[b]
+        p3 = cube + 1
+        tets[:, q, 0] = gidx(p0)
+        tets[:, q, 1] = gidx(p1)
+        tets[:, q, 2] = gidx(p2)
+        tets[:, q, 3] = gidx(p3)
+    cube_of_tet = np.repeat(cube, 6, axis=0)
+    return tets.reshape(-1, 4), cube_of_tet
+
+
+def _grid_boundary_faces(n: int, tets: np.ndarray, kind_of_plane):
+    """Faces of the Kuhn tets lying in one of the 6 planes of the index box.
+
+    kind_of_plane(axis, side) -> BC kind.  Classification uses integer grid
+    coordinates only.
+    """
+    m = n + 1
+    ijk = np.stack([tets % m, (tets // m) % m, tets // (m * m)], axis=2)  # [T,4,3]
+    faces, kinds = [], []
+    for drop in range(4):
+        keep = [c for c in range(4) if c != drop]
+        fv = tets[:, keep]
+        fijk = ijk[:, keep, :]
+        for axis in range(3):
+            for side, val in ((0, 0), (1, n)):
+                on = np.all(fijk[:, :, axis] == val, axis=1)
+                if on.any():
+                    faces.append(np.sort(fv[on], axis=1))
+                    kinds.append(np.full(on.sum(), kind_of_plane(axis, side), dtype=np.int8))
+    faces = np.concatenate(faces)
+    kinds = np.concatenate(kinds)
+    order = np.lexsort((faces[:, 2], faces[:, 1], faces[:, 0]))
+    return faces[order].astype(np.int32), kinds[order]
+
+
+def unit_cube(n: int, bc: int = BC_IMPEDANCE) -> Mesh:
+    """[0,1]^3 as an n^3 Kuhn grid; every boundary face gets kind `bc`."""
+    tets, cube = _kuhn_topology(n)
+    m = n + 1
+    g = np.arange(m) / n
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    bf, bk = _grid_boundary_faces(n, tets, lambda a, s: bc)
+    return Mesh(xyz=xyz, tets=tets.astype(np.int32), bfaces=bf, bface_kind=bk,
+                grid_n=n, cube_of_tet=cube.astype(np.int32))
+
+
+def chamber_cylinder(n: int, radius: float = 0.15, height: float = 0.28) -> Mesh:
+    """Cylindrical chamber: Kuhn grid on [-1,1]^2 x [0,1] mapped to a cylinder.
+
+    (u,v) -> R (u sqrt(1 - v^2/2), v sqrt(1 - u^2/2)), w -> H w; straight-sided
+    tets.  Lateral wall and bottom are metallic (PEC), the top is an
+    impedance boundary (Sec. 2: metallic bottom, impedance top).
+    """
+    tets, cube = _kuhn_topology(n)
+    m = n + 1
+    g = np.arange(m)
+    kk, jj, ii = np.meshgrid(g, g, g, indexing="ij")
+    u = -1.0 + 2.0 * ii.ravel() / n
+    v = -1.0 + 2.0 * jj.ravel() / n
+    w = kk.ravel() / n
+    x = radius * u * np.sqrt(1.0 - 0.5 * v * v)
+    y = radius * v * np.sqrt(1.0 - 0.5 * u * u)
+    xyz = np.stack([x, y, height * w], axis=1)
+
+    def kind(axis, side):
+        if axis == 2 and side == 1:
+            return BC_IMPEDANCE
+        return BC_PEC
+
+    bf, bk = _grid_boundary_faces(n, tets, kind)
+    return Mesh(xyz=xyz, tets=tets.astype(np.int32), bfaces=bf, bface_kind=bk,
+                grid_n=n, cube_of_tet=cube.astype(np.int32))
+
+
+def centroids(mesh: Mesh) -> np.ndarray:
+    return mesh.xyz[mesh.tets].mean(axis=1)
+
+
+# --------------------------------------------------------------------------
+# permittivity maps
+# --------------------------------------------------------------------------
+
+EPS_MATCHING = 44.0 + 20.0j   # matching medium, Sec. 5.1 (conjugated)
+EPS_HEAD = 40.0 + 15.0j
+
+
+def chamber_eps(mesh: Mesh, seed: int):
+    """Background medium, a seeded ellipsoidal head and one spherical inclusion.
+
+    The inclusion changes the head permittivity by +-20 % (sign from the
+    seed), mimicking the two stroke types of the introduction.
+    Returns (eps[T], description dict).
+    """
+    rng = np.random.default_rng(seed)
+    c = centroids(mesh)
+    centre = np.array([0.0, 0.0, 0.14]) + rng.uniform(-0.01, 0.01, 3)
+    axes = np.array([0.08, 0.10, 0.09])
+    theta = rng.uniform(0.0, 2.0 * math.pi)
+    ct, st = math.cos(theta), math.sin(theta)
+    rot = np.array([[ct, -st, 0.0], [st, ct, 0.0], [0.0, 0.0, 1.0]])
+    loc = (c - centre) @ rot              # coordinates in the head frame
+    in_head = np.sum((loc / axes) ** 2, axis=1) <= 1.0
+    r_inc = rng.uniform(0.01, 0.02)
+    # inclusion centre: inside the head, at most half-way to its surface
+    off = rng.uniform(-0.5, 0.5, 3) * (axes - r_inc)
+    inc_centre = centre + rot @ off
+    in_inc = np.sum((c - inc_centre) ** 2, axis=1) <= r_inc ** 2
+    sign = 1.0 if rng.uniform() < 0.5 else -1.0
+    eps = np.full(len(c), EPS_MATCHING, dtype=np.complex128)
+    eps[in_head] = EPS_HEAD
+    eps[in_inc & in_head] = EPS_HEAD * (1.0 + 0.2 * sign)
+    info = dict(head_centre=centre, head_theta=theta, inc_centre=inc_centre,
+                inc_radius=r_inc, inc_sign=sign)
+    return eps, info
+
+
+# --------------------------------------------------------------------------
+# partitions
+# --------------------------------------------------------------------------
+
+def box_partition(mesh: Mesh, box: int) -> tuple[np.ndarray, int]:
+    """Core subdomain = box of box^3 grid cubes; id in lexicographic box order."""
+    n = mesh.grid_n
+    nb = -(-n // box)
+    b = mesh.cube_of_tet // box
+    part = b[:, 0] + nb * (b[:, 1] + nb * b[:, 2])
+    return part.astype(np.int32), nb ** 3
+
+
+def rcb_partition(points: np.ndarray, n_sub: int, weights=None) -> np.ndarray:
+    """Recursive coordinate bisection of element centroids into n_sub parts.
+
+    Each split cuts the longest bounding-box axis; elements are ordered by
+    (coordinate, element id) and divided in proportion to the number of
+    leaves on each side.  Deterministic.
+    """
+    npts = len(points)
+    part = np.empty(npts, dtype=np.int32)
+    ids = np.arange(npts)
+    stack = [(ids, 0, n_sub)]
+    while stack:
+        sel, first, cnt = stack.pop()
+        if cnt == 1:
+            part[sel] = first
+            continue
+        p = points[sel]
+        axis = int(np.argmax(p.max(axis=0) - p.min(axis=0)))
+        order = np.lexsort((sel, p[:, axis]))
+        left = cnt // 2
+        cut = int(round(len(sel) * left / cnt))
+        stack.append((sel[order[:cut]], first, left))
+        stack.append((sel[order[cut:]], first + left, cnt - left))
+    return part
+
+
+# --------------------------------------------------------------------------
+# sources
+# --------------------------------------------------------------------------
+
+def plane_wave(seed: int) -> Source:
+    """Plane wave with seeded unit direction d and unit polarisation p _|_ d."""
+    rng = np.random.default_rng(seed)
+    g1 = rng.standard_normal(3)
+    u = rng.standard_normal(3)
+    d = g1 / np.linalg.norm(g1)
+    p = u - (u @ d) * d
+    p /= np.linalg.norm(p)
+    return Source(kind=SRC_PLANEWAVE, pol=tuple(complex(x) for x in p), dir=tuple(d))
+
+
+def ring_dipoles(count: int = 32, radius: float = 0.14, z: float = 0.196,
+                 first: int = 0, stride: int = 1) -> list:
+    """z-polarised point dipoles at angles 2 pi (m + 1/2)/count on a ring."""
+    out = []
+    for m in range(first, count, stride):
+        phi = 2.0 * math.pi * (m + 0.5) / count
+        out.append(Source(kind=SRC_DIPOLE,
+                          pos=(radius * math.cos(phi), radius * math.sin(phi), z),
+                          pol=(0j, 0j, 1.0 + 0j)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def cube_planewave_problem(n: int = 8, degree: int = 1, box: int = 4, overlap: int = 1,
+                           eps=1.0 + 0.1j, k0: float = 2.0 * math.pi, seed: int = 0,
+                           n_sources: int = 1) -> Problem:
+    """Unit cube, homogeneous eps, impedance everywhere, plane-wave source(s).
+
+    Default: 8^3 cubes, r=1, 2x2x2 box subdomains, one face-layer overlap,
+    eps = 1+0.1i, k0 = 2 pi (one free-space wavelength per side).
+    """
+    mesh = unit_cube(n)
+    eps_t = np.full(len(mesh.tets), eps, dtype=np.complex128)
+    part, n_sub = box_partition(mesh, box)
+    srcs = [plane_wave(seed + s) for s in range(n_sources)]
+    return Problem(mesh=mesh, eps=eps_t, part=part, n_sub=n_sub, overlap=overlap,
+                   k0=k0, degree=degree, sources=srcs,
+                   name=f"cube n={n} r={degree} box={box} ov={overlap}")
+
+
+def chamber_problem(n: int = 34, degree: int = 2, n_sub: int = 1500, overlap: int = 2,
+                    seed: int = 0, n_sources: int = 1, ring_z: float = 0.196) -> Problem:
+    """Synthetic imaging chamber (cylinder R=0.15 m, H=0.28 m) at 1 GHz.
+
+    Background eps = 44+20i, seeded head ellipsoid eps = 40+15i and a
+    +-20 % spherical inclusion; RCB core partition into n_sub parts;
+    z-polarised dipoles on the ring of radius 0.14 m.
+    """
+    mesh = chamber_cylinder(n)
+    eps, _ = chamber_eps(mesh, seed)
+    part = rcb_partition(centroids(mesh), n_sub)
+    srcs = ring_dipoles(32, 0.14, ring_z)[:n_sources] if n_sources <= 32 else \
+        [s for z in (0.028, 0.084, 0.140, 0.196, 0.252) for s in ring_dipoles(32, 0.14, z)][:n_sources]
+    return Problem(mesh=mesh, eps=eps, part=part, n_sub=n_sub, overlap=overlap,
+                   k0=K0_1GHZ, degree=degree, sources=srcs,
+                   name=f"chamber n={n} r={degree} nsub={n_sub} ov={overlap}")
