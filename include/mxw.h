@@ -1,0 +1,214 @@
+/*
+ * mxw.h -- C ABI of the MI355X (gfx950) library for time-harmonic Maxwell
+ * problems discretised with degree-r Nedelec edge elements and solved by
+ * GMRES preconditioned with overlapping optimized restricted additive
+ * Schwarz (ORAS).
+ *
+ * The operation (Bonazzoli, Dolean, Rapetti, Tournier, "Parallel
+ * preconditioners for high order discretizations arising from full system
+ * modeling for brain microwave imaging"):
+ *   - Sec. 2, eq. (1)-(4) and the weak form: curl curl E - k0^2 eps E = 0 in
+ *     the domain, E x n = 0 on metallic faces, impedance condition on the
+ *     others; the system matrix is A = K - k0^2 M_eps - i beta B, complex
+ *     symmetric (bilinear form, one matrix for every right-hand side);
+ *   - Sec. 3: degree-r generators lambda^k w^e, |k| = r-1, with a fixed
+ *     independent subset (r=1,2,3 -> 6, 20, 45 functions per element);
+ *   - Sec. 4: M^{-1} = sum_s R_s^T D_s A_s^{-1} R_s, A_s with impedance
+ *     transmission conditions on subdomain interfaces;
+ *   - Sec. 5: GMRES preconditioned by it; several right-hand sides are
+ *     processed together (pseudo-block), or in one block Krylov space
+ *     (block GMRES, Sec. 6).
+ *
+ * Conventions used throughout:
+ *   - time dependence exp(-i w t): a lossy medium has Im(eps) > 0 (the
+ *     paper's values are the complex conjugates of the ones passed here);
+ *   - beta on an impedance face = k0 sqrt(Re eps) of the adjacent element;
+ *     the transmission coefficient on an interface face uses the element of
+ *     the subdomain that owns the face;
+ *   - global unknowns: edges (lexicographic vertex pairs) then faces
+ *     (lexicographic triples) then elements (input order), each entity's
+ *     unknowns in a fixed order; unknowns on metallic faces are removed;
+ *   - overlap: each layer adds the elements sharing a face with the
+ *     subdomain; the partition of unity is Boolean (an unknown belongs to the
+ *     lowest core subdomain id among the elements that contain its entity);
+ *   - complex numbers are interleaved (re, im) doubles.
+ *
+ * Ownership: the caller owns every array it passes; create calls copy what
+ * they keep, so inputs may be freed on return.  Outputs are allocated by the
+ * caller.  Errors: every call returns an mxw_status; mxw_last_error() gives
+ * the message of the last failing call on the calling thread.  A problem is
+ * immutable after creation except through mxw_problem_factor; solves on one
+ * problem must not overlap in time (they share the Krylov workspace).
+ */
+#ifndef MXW_H
+#define MXW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mxw_status;
+enum {
+  MXW_OK = 0,
+  MXW_EINVAL = -1,      /* invalid argument or inconsistent mesh data */
+  MXW_ENOMEM = -2,      /* device or host allocation failed, or budget exceeded */
+  MXW_ENOTCONV = -3,    /* max_iters reached; outputs hold the last iterate */
+  MXW_ESINGULAR = -4,   /* zero pivot in a local LU factorisation */
+  MXW_EBREAKDOWN = -5,  /* Krylov breakdown without convergence */
+  MXW_EDEVICE = -6,     /* a HIP runtime call failed */
+  MXW_EBUSY = -7        /* ticket not finished */
+};
+
+enum { MXW_BC_PEC = 0, MXW_BC_IMPEDANCE = 1 };
+/* local factor precision: FP64 everywhere, or complex-FP32 local LU/solves
+ * with everything else (assembly, SpMV, Arnoldi, least squares) in FP64 */
+enum { MXW_FP64 = 0, MXW_MIXED = 1 };
+enum { MXW_SRC_DIPOLE = 0, MXW_SRC_PLANEWAVE = 1 };
+enum { MXW_KRYLOV_PSEUDOBLOCK = 0, MXW_KRYLOV_BLOCK = 1 };
+/* preconditioner variants (Sec. 4): ORAS (default), OAS (no D_s),
+ * RAS (Dirichlet transmission: A_s = R_s A R_s^T, with D_s) */
+enum { MXW_PREC_ORAS = 0, MXW_PREC_OAS = 1, MXW_PREC_RAS = 2 };
+
+typedef struct {
+  int64_t n_vertices;
+  const double* xyz;          /* [n_vertices][3] */
+  int64_t n_tets;
+  const int32_t* tets;        /* [n_tets][4], 0-based vertex ids, any order */
+  const double* eps;          /* [n_tets][2] relative permittivity (re, im) */
+  int64_t n_bfaces;
+  const int32_t* bfaces;      /* [n_bfaces][3]; exactly the faces with one tet */
+  const int8_t* bface_kind;   /* [n_bfaces] MXW_BC_* */
+  const int32_t* part;        /* [n_tets] core subdomain id in [0, n_sub) */
+  int32_t n_sub;
+  int32_t overlap_layers;     /* >= 0 face-adjacency layers */
+  double k0;                  /* free-space wavenumber, same length unit as xyz */
+  int32_t degree;             /* r in {1, 2, 3} */
+  int32_t precision;          /* MXW_FP64 | MXW_MIXED */
+  int32_t prec_variant;       /* MXW_PREC_* */
+  int32_t reserved;
+} mxw_problem_desc;
+
+typedef struct {
+  int32_t kind;               /* MXW_SRC_* */
+  int32_t reserved;
+  double pos[3];              /* dipole position */
+  double pol_re[3];           /* dipole moment / plane-wave polarisation */
+  double pol_im[3];
+  double dir[3];              /* plane-wave unit direction */
+} mxw_source;
+
+typedef struct {
+  double tol;                 /* true relative residual target ||b-Ax||/||b|| */
+  int32_t restart;            /* m, Krylov steps per cycle (1..200) */
+  int32_t max_iters;          /* total Arnoldi steps (block steps for block GMRES) */
+  int32_t krylov;             /* MXW_KRYLOV_* */
+  int32_t use_graph;          /* 1: run each Arnoldi step as a captured HIP graph */
+} mxw_solve_opts;
+
+typedef struct {
+  int64_t ndof;               /* global unknowns after metallic elimination */
+  int64_t nnz;                /* structural non-zeros of A */
+  int32_t n_sub;
+  int32_t nloc;               /* unknowns per element: 6, 20, 45 */
+  int64_t sum_ns;             /* sum of local sizes n_s */
+  int64_t max_ns;
+  double sum_ns2;             /* sum of n_s^2 (dense factor entries) */
+  double sum_ns3;             /* sum of n_s^3 */
+  int64_t n_iface;            /* interface faces over all subdomains */
+  int64_t n_imp_faces;        /* impedance boundary faces */
+} mxw_layout_info;
+
+typedef struct mxw_layout mxw_layout;
+typedef struct mxw_problem mxw_problem;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char* mxw_last_error(void);
+
+/* ---- host-side setup (no device needed) -------------------------------- */
+
+/* Entities, unknown numbering (Sec. 3-4), sparsity pattern of A, overlapping
+ * subdomains N_s with their partition of unity D_s and interface faces
+ * (Sec. 4).  Validates the mesh: vertex ids in range, distinct vertices,
+ * non-zero volumes, finite eps, boundary faces equal to the faces with one
+ * tet, part ids in range.  Returns MXW_EINVAL with a message otherwise. */
+mxw_status mxw_layout_create(const mxw_problem_desc* desc, mxw_layout** out);
+void mxw_layout_destroy(mxw_layout* layout);
+mxw_status mxw_layout_get_info(const mxw_layout* layout, mxw_layout_info* info);
+/* Entity of each global unknown: kind 0 edge / 1 face / 2 element, entity id
+ * in the numbering above, index within the entity.  Arrays of length ndof. */
+mxw_status mxw_export_dofs(const mxw_layout* layout, int8_t* ent_kind, int64_t* ent_id,
+                           int16_t* ent_local);
+/* CSR pattern of A: rowptr [ndof+1], cols [nnz] ascending in each row. */
+mxw_status mxw_export_pattern(const mxw_layout* layout, int64_t* rowptr, int32_t* cols);
+/* N_s of subdomain s (sorted global unknowns) and D_s (0/1).  Pass NULL for
+ * dofs/pou to query n_s only. */
+mxw_status mxw_export_subdomain(const mxw_layout* layout, int32_t s, int64_t* n_s,
+                                int64_t* dofs, uint8_t* pou);
+/* Device bytes a problem built from this layout needs, for nrhs columns and
+ * the given Krylov options (admission control). */
+mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int32_t nrhs,
+                                const mxw_solve_opts* opts, uint64_t* bytes);
+
+/* ---- device problem ---------------------------------------------------- */
+
+/* Builds the device operator: element matrices (FP64), CSR assembly of A,
+ * dense local matrices A_s and (unless defer_factor) their batched LU
+ * factorisation with partial pivoting, all on `stream` (a hipStream_t; NULL
+ * = default stream) of the current device.  Blocks until done.
+ * hbm_budget (bytes, 0 = no limit) rejects problems whose footprint exceeds
+ * it with MXW_ENOMEM before allocating. */
+mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64_t hbm_budget,
+                              int32_t defer_factor, mxw_problem** out);
+void mxw_problem_destroy(mxw_problem* prob);
+mxw_status mxw_problem_get_info(const mxw_problem* prob, mxw_layout_info* info);
+/* Factorises every A_s in place (batched LU, partial pivoting). Idempotent.
+ * MXW_ESINGULAR names the first subdomain with a zero pivot. */
+mxw_status mxw_problem_factor(mxw_problem* prob, void* stream);
+
+/* Values of A in the exported CSR pattern, host complex128 [nnz]. */
+mxw_status mxw_problem_export_matrix(const mxw_problem* prob, double* vals);
+/* Dense A_s before factorisation (column-major, host complex128 [n_s*n_s]).
+ * Only valid while the problem is not yet factorised. */
+mxw_status mxw_problem_export_local(const mxw_problem* prob, int32_t s, double* a_s);
+
+/* Right-hand sides b [nrhs][ndof] (device complex128) for the sources:
+ * dipole b_i = p . phi_i(x_s) in the lowest-index element containing x_s;
+ * plane wave b_i = int g . phi_i over impedance faces, g from
+ * E = p exp(i k0 sqrt(eps) d.x). */
+mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev,
+                           void* stream);
+/* y = A x for nrhs device vectors [nrhs][ndof] complex128. */
+mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_dev, double* y_dev,
+                               void* stream);
+/* z = M^{-1} v (ORAS: restrict, local LU solves, Boolean prolongation). */
+mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double* v_dev, double* z_dev,
+                                  void* stream);
+
+/* Solves A x_j = b_j for nrhs sources with FGMRES + ORAS.  E_out: complex128
+ * [nrhs][ndof] on the device (E_out_is_device = 1) or host.  iters_out
+ * [nrhs] and relres_out [nrhs] (true relative residuals) may be NULL.
+ * Returns MXW_ENOTCONV if any column missed tol within max_iters. */
+mxw_status mxw_solve(mxw_problem* prob, int32_t nrhs, const mxw_source* src,
+                     const mxw_solve_opts* opts, void* stream, double* E_out,
+                     int32_t E_out_is_device, int32_t* iters_out, double* relres_out);
+/* Same with right-hand sides given directly (device complex128 [nrhs][ndof]). */
+mxw_status mxw_solve_rhs(mxw_problem* prob, int32_t nrhs, const double* b_dev,
+                         const mxw_solve_opts* opts, void* stream, double* x_dev,
+                         int32_t* iters_out, double* relres_out);
+
+/* ---- instrumentation --------------------------------------------------- */
+
+/* Per-kernel timing with HIP events on the launching stream (off by default). */
+mxw_status mxw_set_timing(int32_t enabled);
+/* Accumulated time (ms) and launch count of a kernel class since the last
+ * reset: names "lu", "local_solve", "spmv", "cgs", "assemble", "local_assemble". */
+mxw_status mxw_get_timing(const char* name, double* total_ms, int64_t* launches);
+mxw_status mxw_reset_timing(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MXW_H */

@@ -1,0 +1,173 @@
+"""Python front end of libmxw: host layouts and device problems.
+
+PyTorch provides device memory and the stream; every computation runs in the
+library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as B
+
+
+class Layout:
+    """Host-side setup: unknown numbering, CSR pattern, subdomains (no GPU)."""
+
+    def __init__(self, desc: B.Desc):
+        self.desc = desc
+        h = C.c_void_p()
+        B.check(B.lib().mxw_layout_create(C.byref(desc.c), C.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        return cls(B.Desc.from_problem(prob, **kw))
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            B.lib().mxw_layout_destroy(self.h)
+            self.h = None
+
+    def info(self) -> B.LayoutInfo:
+        i = B.LayoutInfo()
+        B.check(B.lib().mxw_layout_get_info(self.h, C.byref(i)))
+        return i
+
+    def dofs(self):
+        n = self.info().ndof
+        k = np.empty(n, np.int8)
+        e = np.empty(n, np.int64)
+        l = np.empty(n, np.int16)
+        B.check(B.lib().mxw_export_dofs(self.h, k.ctypes.data, e.ctypes.data, l.ctypes.data))
+        return k, e, l
+
+    def pattern(self):
+        i = self.info()
+        rp = np.empty(i.ndof + 1, np.int64)
+        ci = np.empty(i.nnz, np.int32)
+        B.check(B.lib().mxw_export_pattern(self.h, rp.ctypes.data, ci.ctypes.data))
+        return rp, ci
+
+    def subdomain(self, s: int):
+        n = C.c_int64()
+        B.check(B.lib().mxw_export_subdomain(self.h, s, C.byref(n), None, None))
+        d = np.empty(n.value, np.int64)
+        w = np.empty(n.value, np.uint8)
+        B.check(B.lib().mxw_export_subdomain(self.h, s, C.byref(n), d.ctypes.data, w.ctypes.data))
+        return d, w
+
+    def footprint(self, precision=B.MXW_FP64, nrhs=1, restart=50) -> int:
+        out = C.c_uint64()
+        opts = B.solve_opts(restart=restart)
+        B.check(B.lib().mxw_layout_footprint(self.h, precision, nrhs, C.byref(opts), C.byref(out)))
+        return out.value
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Problem:
+    """Device operator: assembled A, local matrices, batched LU factors."""
+
+    def __init__(self, desc: B.Desc, hbm_budget: int = 0, defer_factor: bool = False):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a GPU is required for mxw.Problem")
+        self.desc = desc
+        h = C.c_void_p()
+        st = B.lib().mxw_problem_create(C.byref(desc.c), _stream(), hbm_budget, int(defer_factor), C.byref(h))
+        self.h = h
+        self.create_status = st
+        if st != B.MXW_OK and not (st == B.MXW_ESINGULAR and h.value):
+            B.check(st)
+        self._info = self.info()
+
+    @classmethod
+    def from_problem(cls, prob, precision=B.MXW_FP64, variant=B.MXW_PREC_ORAS, **kw):
+        return cls(B.Desc.from_problem(prob, precision, variant), **kw)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            B.lib().mxw_problem_destroy(self.h)
+            self.h = None
+
+    def info(self) -> B.LayoutInfo:
+        i = B.LayoutInfo()
+        B.check(B.lib().mxw_problem_get_info(self.h, C.byref(i)))
+        return i
+
+    @property
+    def ndof(self) -> int:
+        return self._info.ndof
+
+    def factor(self):
+        return B.check(B.lib().mxw_problem_factor(self.h, _stream()))
+
+    def matrix_values(self) -> np.ndarray:
+        v = np.empty(self._info.nnz, np.complex128)
+        B.check(B.lib().mxw_problem_export_matrix(self.h, v.ctypes.data))
+        return v
+
+    def local_matrix(self, s: int, n_s: int) -> np.ndarray:
+        a = np.empty((n_s, n_s), np.complex128, order="F")
+        B.check(B.lib().mxw_problem_export_local(self.h, s, a.ctypes.data))
+        return a
+
+    def rhs(self, sources):
+        import torch
+        b = torch.empty((len(sources), self.ndof), dtype=torch.complex128, device="cuda")
+        src = B.make_sources(sources)
+        B.check(B.lib().mxw_problem_rhs(self.h, len(sources), src, b.data_ptr(), _stream()))
+        return b
+
+    def apply_A(self, x):
+        import torch
+        x = x.contiguous()
+        y = torch.empty_like(x)
+        B.check(B.lib().mxw_problem_apply_A(self.h, x.shape[0], x.data_ptr(), y.data_ptr(), _stream()))
+        return y
+
+    def apply_prec(self, v):
+        import torch
+        v = v.contiguous()
+        z = torch.empty_like(v)
+        B.check(B.lib().mxw_problem_apply_prec(self.h, v.shape[0], v.data_ptr(), z.data_ptr(), _stream()))
+        return z
+
+    def solve_rhs(self, b, tol=1e-8, restart=50, max_iters=5000, krylov=B.MXW_KRYLOV_PSEUDOBLOCK,
+                  use_graph=0, allow_notconv=False):
+        import torch
+        b = b.contiguous()
+        nrhs = b.shape[0]
+        x = torch.empty_like(b)
+        it = np.zeros(nrhs, np.int32)
+        rr = np.zeros(nrhs, np.float64)
+        opts = B.solve_opts(tol, restart, max_iters, krylov, use_graph)
+        st = B.lib().mxw_solve_rhs(self.h, nrhs, b.data_ptr(), C.byref(opts), _stream(), x.data_ptr(),
+                                   it.ctypes.data, rr.ctypes.data)
+        allowed = (B.MXW_OK, B.MXW_ENOTCONV, B.MXW_EBREAKDOWN) if allow_notconv else (B.MXW_OK,)
+        status = B.check(st, allowed)
+        return x, it, rr, status
+
+    def solve(self, sources, **kw):
+        b = self.rhs(sources)
+        return self.solve_rhs(b, **kw)
+
+
+def timing(enabled: bool = True):
+    B.check(B.lib().mxw_set_timing(int(enabled)))
+
+
+def kernel_time(name: str):
+    t = C.c_double()
+    n = C.c_int64()
+    B.check(B.lib().mxw_get_timing(name.encode(), C.byref(t), C.byref(n)))
+    return t.value, n.value
+
+
+def reset_timing():
+    B.check(B.lib().mxw_reset_timing())

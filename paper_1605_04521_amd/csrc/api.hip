@@ -1,0 +1,1037 @@
+// C ABI of the library: layouts, device problems, ORAS application and the
+// FGMRES driver (Sec. 4-5 of the paper).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "mxw_internal.h"
+
+namespace mxw {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+// ---------------------------------------------------------------------------
+// kernel timing with HIP events on the launching stream
+// ---------------------------------------------------------------------------
+struct TimingRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimingRec> g_pending;
+static std::map<std::string, std::pair<double, int64_t>> g_totals;
+
+struct ScopedTimer {
+  hipStream_t st;
+  const char* name;
+  hipEvent_t a = nullptr, b = nullptr;
+  ScopedTimer(hipStream_t s, const char* n) : st(s), name(n) {
+    if (!g_timing) return;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipEventRecord(a, st);
+  }
+  ~ScopedTimer() {
+    if (!a) return;
+    hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back({name, a, b});
+  }
+};
+
+static void flush_timing() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& r : g_pending) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    auto& t = g_totals[r.name];
+    t.first += ms;
+    t.second += 1;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+struct DevMem {
+  std::vector<void*> ptrs;
+  uint64_t bytes = 0;
+  ~DevMem() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  template <class T>
+  T* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    return static_cast<T*>(p);
+  }
+  void reset() {
+    for (void* p : ptrs) hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  void release(void* p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      hipFree(p);
+      ptrs.erase(it);
+    }
+  }
+};
+
+}  // namespace mxw
+
+using namespace mxw;
+
+struct mxw_layout {
+  Layout L;
+};
+
+struct KrylovWork {
+  int nrhs = 0, m = 0;
+  int64_t ndof = 0;
+  DevMem mem;
+  double2 *V = nullptr, *Z = nullptr, *W = nullptr, *X = nullptr, *Rv = nullptr, *YS = nullptr;
+  double2 *h1 = nullptr, *h2 = nullptr, *part = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+  double *cs = nullptr, *hn = nullptr, *w0 = nullptr, *npart = nullptr, *est = nullptr, *beta = nullptr;
+  int *active = nullptr, *jd = nullptr;
+  double* host = nullptr;   // pinned: est, hn, w0 for every column
+};
+
+struct mxw_problem {
+  Layout L;
+  int device = 0;
+  DevMem mem;
+  // geometry / basis
+  double* xyz = nullptr;
+  int* tets = nullptr;
+  double* eps = nullptr;
+  int* tet_dofs = nullptr;
+  Term *phi = nullptr, *curl = nullptr, *fphi = nullptr;
+  double2* AT = nullptr;
+  double* BF = nullptr;
+  int *ft_vert = nullptr, *ft_dofs = nullptr;
+  // global matrix
+  int64_t* rowptr = nullptr;
+  int* cols = nullptr;
+  double2* vals = nullptr;
+  int* dof_ent = nullptr;
+  int64_t *ent_tet_ptr = nullptr, *ent_imp_ptr = nullptr;
+  int *ent_tets = nullptr, *ent_imps = nullptr;
+  int *imp_ft = nullptr, *imp_opp = nullptr;
+  double *imp_beta = nullptr, *imp_eps = nullptr;
+  double *gx = nullptr, *gw = nullptr;
+  int nq = 0;
+  // subdomains
+  int64_t *foff = nullptr, *poff = nullptr, *sub_tet_ptr = nullptr, *sub_face_ptr = nullptr;
+  int *nsz = nullptr, *lds = nullptr, *perm = nullptr, *sub_dofs = nullptr, *sub_tets = nullptr, *sub_lmap = nullptr;
+  int *sub_face_ft = nullptr, *sub_face_lmap = nullptr, *info = nullptr, *order = nullptr;
+  uint8_t* pou = nullptr;
+  double* sub_face_coef = nullptr;
+  int64_t *gall_ptr = nullptr, *gall_pos = nullptr;
+  void* F = nullptr;
+  void* lu_scratch = nullptr;
+  uint64_t factor_elems = 0;
+  std::vector<int64_t> h_foff;
+  std::vector<int> h_lds, h_order;
+  bool factored = false;
+  bool mixed = false;
+  int spmv_group = 16;
+  KrylovWork kw;
+};
+
+namespace {
+
+mxw_status dev_fail(const char* what, hipError_t e) {
+  std::ostringstream os;
+  os << what << ": " << hipGetErrorString(e);
+  set_error(os.str());
+  return MXW_EDEVICE;
+}
+
+#define HIP_CHECK(x)                                  \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) return dev_fail(#x, e_);    \
+  } while (0)
+
+template <class T>
+mxw_status upload(DevMem& mem, T*& dst, const std::vector<T>& src, hipStream_t st) {
+  dst = mem.alloc<T>(src.size());
+  if (!dst) {
+    set_error("device allocation failed");
+    return MXW_ENOMEM;
+  }
+  if (!src.empty()) HIP_CHECK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return MXW_OK;
+}
+
+#define TRY(x)                    \
+  do {                            \
+    mxw_status s_ = (x);          \
+    if (s_ != MXW_OK) return s_;  \
+  } while (0)
+
+int64_t round_ld(int64_t n) { return (n + 7) / 8 * 8; }
+
+// Gauss-Legendre nodes and weights on [0,1] (Newton iteration on P_n).
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? z : p1;
+      double pm = (n == 1) ? 1.0 : p0;
+      double dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pn = (n == 1) ? z : p1;
+    double pm = (n == 1) ? 1.0 : p0;
+    double dp = n * (z * pn - pm) / (z * z - 1.0);
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);   // = 0.5 * 2/((1-z^2) P'^2)
+  }
+}
+
+uint64_t factor_bytes(const Layout& L, int precision) {
+  uint64_t e = 0;
+  for (int s = 0; s < L.n_sub; ++s) {
+    int64_t n = L.sub_dof_ptr[s + 1] - L.sub_dof_ptr[s];
+    e += 2 * (uint64_t)round_ld(n) * n;
+  }
+  return e * (precision == MXW_MIXED ? 4 : 8);
+}
+
+uint64_t krylov_bytes(int64_t ndof, int nrhs, int m) {
+  const int64_t nblk = (ndof + 2047) / 2048;
+  uint64_t b = 0;
+  b += (uint64_t)nrhs * (2 * m + 1) * ndof * 16;     // V, Z
+  b += (uint64_t)nrhs * 3 * ndof * 16;               // W, X, R
+  b += (uint64_t)nrhs * nblk * (m + 1) * 16;
+  b += (uint64_t)nrhs * (m + 1) * (m + 8) * 16;
+  return b;
+}
+
+uint64_t base_bytes(const Layout& L) {
+  uint64_t b = 0;
+  const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
+  b += L.xyz.size() * 8 + L.tets.size() * 4 + L.eps.size() * 8 + L.tet_dofs.size() * 4;
+  b += (uint64_t)L.nt * nloc * nloc * 16;                      // element matrices
+  b += (uint64_t)L.ft_face.size() * nfloc * (nfloc * 8 + 4) + L.ft_vert.size() * 4;
+  b += L.rowptr.size() * 8 + L.cols.size() * 4 + L.cols.size() * 16;
+  b += L.dof_ent.size() * 4 + L.ent_tet_ptr.size() * 8 + L.ent_tets.size() * 4;
+  b += L.ent_imp_ptr.size() * 8 + L.ent_imps.size() * 4;
+  b += L.sub_dofs.size() * (4 + 1 + 4) + L.sub_tets.size() * 4 + L.sub_lmap.size() * 4;
+  b += L.sub_face_ft.size() * 12 + L.sub_face_lmap.size() * 4;
+  b += (uint64_t)L.n_sub * (8 * 4 + 4 * 4);
+  b += (uint64_t)L.sum_ns * 8 + (uint64_t)L.ndof * 8;
+  return b;
+}
+
+mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
+  KrylovWork& k = P->kw;
+  if (k.nrhs >= nrhs && k.m == m && k.ndof == P->L.ndof && k.V) return MXW_OK;
+  k.mem.reset();
+  if (k.host) {
+    hipHostFree(k.host);
+    k.host = nullptr;
+  }
+  const int64_t n = P->L.ndof;
+  const int maxv = m + 1;
+  const int nblk = red_blocks(n);
+  k.nrhs = nrhs;
+  k.m = m;
+  k.ndof = n;
+  k.V = k.mem.alloc<double2>((size_t)nrhs * maxv * n);
+  k.Z = k.mem.alloc<double2>((size_t)nrhs * m * n);
+  k.W = k.mem.alloc<double2>((size_t)nrhs * n);
+  k.X = k.mem.alloc<double2>((size_t)nrhs * n);
+  k.Rv = k.mem.alloc<double2>((size_t)nrhs * n);
+  k.YS = P->L.variant == MXW_PREC_OAS ? k.mem.alloc<double2>((size_t)nrhs * P->L.sum_ns) : nullptr;
+  k.h1 = k.mem.alloc<double2>((size_t)nrhs * maxv);
+  k.h2 = k.mem.alloc<double2>((size_t)nrhs * maxv);
+  k.part = k.mem.alloc<double2>((size_t)nrhs * nblk * maxv);
+  k.H = k.mem.alloc<double2>((size_t)nrhs * maxv * m);
+  k.sn = k.mem.alloc<double2>((size_t)nrhs * maxv);
+  k.g = k.mem.alloc<double2>((size_t)nrhs * (maxv + 1));
+  k.y = k.mem.alloc<double2>((size_t)nrhs * maxv);
+  k.cs = k.mem.alloc<double>((size_t)nrhs * maxv);
+  k.hn = k.mem.alloc<double>(nrhs);
+  k.w0 = k.mem.alloc<double>(nrhs);
+  k.npart = k.mem.alloc<double>((size_t)nrhs * nblk);
+  k.est = k.mem.alloc<double>(nrhs);
+  k.beta = k.mem.alloc<double>(nrhs);
+  k.active = k.mem.alloc<int>(nrhs);
+  k.jd = k.mem.alloc<int>(nrhs);
+  if (!k.V || !k.Z || !k.W || !k.X || !k.Rv || !k.h1 || !k.h2 || !k.part || !k.H || !k.sn || !k.g || !k.y ||
+      !k.cs || !k.hn || !k.w0 || !k.npart || !k.est || !k.beta || !k.active || !k.jd ||
+      (P->L.variant == MXW_PREC_OAS && !k.YS)) {
+    k.V = nullptr;
+    set_error("Krylov workspace allocation failed");
+    return MXW_ENOMEM;
+  }
+  if (hipHostMalloc((void**)&k.host, sizeof(double) * 4 * nrhs) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    return MXW_ENOMEM;
+  }
+  return MXW_OK;
+}
+
+// z = M^{-1} v for ncol columns (device, stride ndof)
+void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vstride, double2* z, int64_t zstride,
+                    int ncol, const int* active, double2* ys) {
+  ScopedTimer tm(st, "local_solve");
+  LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
+                   P->order};
+  const int64_t n = P->L.ndof;
+  const bool oas = P->L.variant == MXW_PREC_OAS;
+  if (P->mixed)
+    launch_local_solve<float>(st, a, (const float*)P->F, v, vstride, z, zstride, oas ? ys : nullptr, P->L.sum_ns, ncol,
+                              active);
+  else
+    launch_local_solve<double>(st, a, (const double*)P->F, v, vstride, z, zstride, oas ? ys : nullptr, P->L.sum_ns,
+                               ncol, active);
+  if (oas) launch_gather_all(st, n, P->gall_ptr, P->gall_pos, ys, P->L.sum_ns, z, zstride, ncol, active);
+}
+
+void spmv_dev(mxw_problem* P, hipStream_t st, const double2* x, double2* y, const double2* b, int ncol,
+              const int* active) {
+  ScopedTimer tm(st, "spmv");
+  const int64_t n = P->L.ndof;
+  launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, x, n, y, n, b, n, ncol, active);
+}
+
+mxw_status check_problem(const mxw_problem* P) {
+  if (!P) {
+    set_error("problem is NULL");
+    return MXW_EINVAL;
+  }
+  return MXW_OK;
+}
+
+template <typename R>
+mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor) {
+  const Layout& L = P->L;
+  LocalAssembleArgs la{L.n_sub, P->foff, P->nsz, P->lds, P->sub_tet_ptr, P->sub_tets, P->sub_lmap, P->AT,
+                       L.basis.nloc, P->sub_face_ptr, P->sub_face_ft, P->sub_face_coef, P->sub_face_lmap, P->BF,
+                       L.basis.nfloc};
+  {
+    ScopedTimer tm(st, "local_assemble");
+    launch_assemble_local<R>(st, la, (R*)P->F);
+  }
+  HIP_CHECK(hipGetLastError());
+  if (factor) {
+    ScopedTimer tm(st, "lu");
+    launch_lu<R>(st, L.n_sub, (R*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (R*)P->lu_scratch, P->info,
+                 P->order);
+  }
+  HIP_CHECK(hipGetLastError());
+  return MXW_OK;
+}
+
+mxw_status factor_impl(mxw_problem* P, hipStream_t st) {
+  if (P->factored) return MXW_OK;
+  if (P->mixed) {
+    const int NB = kLuNB;
+    (void)NB;
+    ScopedTimer tm(st, "lu");
+    launch_lu<float>(st, P->L.n_sub, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (float*)P->lu_scratch,
+                     P->info, P->order);
+  } else {
+    ScopedTimer tm(st, "lu");
+    launch_lu<double>(st, P->L.n_sub, (double*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
+                      (double*)P->lu_scratch, P->info, P->order);
+  }
+  HIP_CHECK(hipGetLastError());
+  std::vector<int> info(P->L.n_sub);
+  HIP_CHECK(hipMemcpyAsync(info.data(), P->info, sizeof(int) * info.size(), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  P->factored = true;
+  for (int s = 0; s < P->L.n_sub; ++s)
+    if (info[s] != 0) {
+      std::ostringstream os;
+      os << "zero pivot in the LU of subdomain " << s << " at column " << info[s] - 1;
+      set_error(os.str());
+      return MXW_ESINGULAR;
+    }
+  return MXW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mxw_last_error(void) { return g_err.c_str(); }
+
+mxw_status mxw_layout_create(const mxw_problem_desc* desc, mxw_layout** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return MXW_EINVAL;
+  }
+  *out = nullptr;
+  std::unique_ptr<mxw_layout> l(new (std::nothrow) mxw_layout());
+  if (!l) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  try {
+    TRY(build_layout(desc, l->L));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  *out = l.release();
+  return MXW_OK;
+}
+
+void mxw_layout_destroy(mxw_layout* layout) { delete layout; }
+
+static void fill_info(const Layout& L, mxw_layout_info* info) {
+  info->ndof = L.ndof;
+  info->nnz = L.rowptr.empty() ? 0 : L.rowptr.back();
+  info->n_sub = L.n_sub;
+  info->nloc = L.basis.nloc;
+  info->sum_ns = L.sum_ns;
+  info->max_ns = L.max_ns;
+  info->sum_ns2 = L.sum_ns2;
+  info->sum_ns3 = L.sum_ns3;
+  info->n_iface = L.n_iface;
+  info->n_imp_faces = (int64_t)L.imp_ft.size();
+}
+
+mxw_status mxw_layout_get_info(const mxw_layout* layout, mxw_layout_info* info) {
+  if (!layout || !info) {
+    set_error("NULL argument");
+    return MXW_EINVAL;
+  }
+  fill_info(layout->L, info);
+  return MXW_OK;
+}
+
+mxw_status mxw_export_dofs(const mxw_layout* layout, int8_t* ent_kind, int64_t* ent_id, int16_t* ent_local) {
+  if (!layout || !ent_kind || !ent_id || !ent_local) {
+    set_error("NULL argument");
+    return MXW_EINVAL;
+  }
+  const Layout& L = layout->L;
+  std::copy(L.ent_kind.begin(), L.ent_kind.end(), ent_kind);
+  std::copy(L.ent_id.begin(), L.ent_id.end(), ent_id);
+  std::copy(L.ent_local.begin(), L.ent_local.end(), ent_local);
+  return MXW_OK;
+}
+
+mxw_status mxw_export_pattern(const mxw_layout* layout, int64_t* rowptr, int32_t* cols) {
+  if (!layout || !rowptr || !cols) {
+    set_error("NULL argument");
+    return MXW_EINVAL;
+  }
+  std::copy(layout->L.rowptr.begin(), layout->L.rowptr.end(), rowptr);
+  std::copy(layout->L.cols.begin(), layout->L.cols.end(), cols);
+  return MXW_OK;
+}
+
+mxw_status mxw_export_subdomain(const mxw_layout* layout, int32_t s, int64_t* n_s, int64_t* dofs, uint8_t* pou) {
+  if (!layout || !n_s) {
+    set_error("NULL argument");
+    return MXW_EINVAL;
+  }
+  const Layout& L = layout->L;
+  if (s < 0 || s >= L.n_sub) {
+    set_error("subdomain id out of range");
+    return MXW_EINVAL;
+  }
+  const int64_t b = L.sub_dof_ptr[s], e = L.sub_dof_ptr[s + 1];
+  *n_s = e - b;
+  if (dofs)
+    for (int64_t q = b; q < e; ++q) dofs[q - b] = L.sub_dofs[q];
+  if (pou) std::copy(L.sub_pou.begin() + b, L.sub_pou.begin() + e, pou);
+  return MXW_OK;
+}
+
+mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int32_t nrhs,
+                                const mxw_solve_opts* opts, uint64_t* bytes) {
+  if (!layout || !bytes || nrhs < 0) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  const int m = opts ? opts->restart : 50;
+  const Layout& L = layout->L;
+  *bytes = base_bytes(L) + factor_bytes(L, precision) + krylov_bytes(L.ndof, std::max(nrhs, 1), m);
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64_t hbm_budget, int32_t defer_factor,
+                              mxw_problem** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return MXW_EINVAL;
+  }
+  *out = nullptr;
+  std::unique_ptr<mxw_problem> P(new (std::nothrow) mxw_problem());
+  if (!P) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  try {
+    TRY(build_layout(desc, P->L));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  Layout& L = P->L;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_CHECK(hipGetDevice(&P->device));
+  P->mixed = L.precision == MXW_MIXED;
+  const uint64_t need = base_bytes(L) + factor_bytes(L, L.precision);
+  if (hbm_budget && need > hbm_budget) {
+    std::ostringstream os;
+    os << "problem needs " << need << " device bytes, budget is " << hbm_budget;
+    set_error(os.str());
+    return MXW_ENOMEM;
+  }
+  if ((uint64_t)L.max_ns * 2 * (P->mixed ? 4 : 8) > 150 * 1024) {
+    std::ostringstream os;
+    os << "largest subdomain has " << L.max_ns << " unknowns; the local solve keeps one local vector in LDS "
+       << "(at most " << 150 * 1024 / (2 * (P->mixed ? 4 : 8)) << " unknowns in this precision)";
+    set_error(os.str());
+    return MXW_EINVAL;
+  }
+  const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
+  DevMem& M = P->mem;
+  TRY(upload(M, P->xyz, L.xyz, st));
+  TRY(upload(M, P->tets, L.tets, st));
+  TRY(upload(M, P->eps, L.eps, st));
+  TRY(upload(M, P->tet_dofs, L.tet_dofs, st));
+  TRY(upload(M, P->phi, L.basis.phi, st));
+  TRY(upload(M, P->curl, L.basis.curl, st));
+  TRY(upload(M, P->fphi, L.basis.fphi, st));
+  TRY(upload(M, P->ft_vert, L.ft_vert, st));
+  TRY(upload(M, P->ft_dofs, L.ft_dofs, st));
+  TRY(upload(M, P->rowptr, L.rowptr, st));
+  TRY(upload(M, P->cols, L.cols, st));
+  TRY(upload(M, P->dof_ent, L.dof_ent, st));
+  TRY(upload(M, P->ent_tet_ptr, L.ent_tet_ptr, st));
+  TRY(upload(M, P->ent_tets, L.ent_tets, st));
+  TRY(upload(M, P->ent_imp_ptr, L.ent_imp_ptr, st));
+  TRY(upload(M, P->ent_imps, L.ent_imps, st));
+  TRY(upload(M, P->imp_ft, L.imp_ft, st));
+  TRY(upload(M, P->imp_beta, L.imp_beta, st));
+  {
+    std::vector<int> opp(L.imp_ft.size());
+    std::vector<double> ie(2 * L.imp_ft.size());
+    for (size_t q = 0; q < L.imp_ft.size(); ++q) {
+      const int32_t f = L.ft_face[L.imp_ft[q]];
+      const int32_t t = L.face_t0[f];
+      const auto& fv = L.faces[f];
+      int o = -1;
+      for (int c = 0; c < 4; ++c) {
+        const int32_t v = L.tets[4 * (int64_t)t + c];
+        if (v != fv[0] && v != fv[1] && v != fv[2]) o = v;
+      }
+      opp[q] = o;
+      ie[2 * q] = L.eps[2 * (int64_t)t];
+      ie[2 * q + 1] = L.eps[2 * (int64_t)t + 1];
+    }
+    TRY(upload(M, P->imp_opp, opp, st));
+    TRY(upload(M, P->imp_eps, ie, st));
+    std::vector<double> gx, gw;
+    P->nq = L.r + 3;
+    gauss_legendre01(P->nq, gx, gw);
+    TRY(upload(M, P->gx, gx, st));
+    TRY(upload(M, P->gw, gw, st));
+  }
+  // subdomain arrays
+  {
+    std::vector<int64_t> foff(L.n_sub), poff(L.n_sub + 1);
+    std::vector<int> nsz(L.n_sub), lds(L.n_sub);
+    uint64_t off = 0;
+    for (int s = 0; s < L.n_sub; ++s) {
+      const int64_t n = L.sub_dof_ptr[s + 1] - L.sub_dof_ptr[s];
+      nsz[s] = (int)n;
+      lds[s] = (int)round_ld(n);
+      foff[s] = (int64_t)off;
+      off += 2 * (uint64_t)lds[s] * n;
+      poff[s] = L.sub_dof_ptr[s];
+    }
+    poff[L.n_sub] = L.sub_dof_ptr[L.n_sub];
+    P->factor_elems = off;
+    P->h_foff = foff;
+    P->h_lds = lds;
+    std::vector<int> order(L.n_sub);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nsz[a] > nsz[b]; });
+    P->h_order = order;
+    TRY(upload(M, P->foff, foff, st));
+    TRY(upload(M, P->poff, poff, st));
+    TRY(upload(M, P->nsz, nsz, st));
+    TRY(upload(M, P->lds, lds, st));
+    TRY(upload(M, P->order, order, st));
+    std::vector<int> sd(L.sub_dofs.begin(), L.sub_dofs.end());
+    TRY(upload(M, P->sub_dofs, sd, st));
+    TRY(upload(M, P->pou, L.sub_pou, st));
+    TRY(upload(M, P->sub_tet_ptr, L.sub_tet_ptr, st));
+    TRY(upload(M, P->sub_tets, L.sub_tets, st));
+    TRY(upload(M, P->sub_lmap, L.sub_lmap, st));
+    TRY(upload(M, P->sub_face_ptr, L.sub_face_ptr, st));
+    TRY(upload(M, P->sub_face_ft, L.sub_face_ft, st));
+    TRY(upload(M, P->sub_face_coef, L.sub_face_coef, st));
+    TRY(upload(M, P->sub_face_lmap, L.sub_face_lmap, st));
+    if (L.variant == MXW_PREC_OAS) {
+      // unknown -> positions in every subdomain's local vector, subdomain order
+      std::vector<int64_t> cnt(L.ndof + 1, 0);
+      for (int64_t q = 0; q < (int64_t)L.sub_dofs.size(); ++q) cnt[L.sub_dofs[q] + 1]++;
+      for (int64_t i = 0; i < L.ndof; ++i) cnt[i + 1] += cnt[i];
+      std::vector<int64_t> pos(L.sub_dofs.size()), fill(cnt.begin(), cnt.end() - 1);
+      for (int64_t q = 0; q < (int64_t)L.sub_dofs.size(); ++q) pos[fill[L.sub_dofs[q]]++] = q;
+      TRY(upload(M, P->gall_ptr, cnt, st));
+      TRY(upload(M, P->gall_pos, pos, st));
+    }
+  }
+  P->perm = M.alloc<int>(L.sum_ns);
+  P->info = M.alloc<int>(L.n_sub);
+  const size_t rsz = P->mixed ? 4 : 8;
+  P->F = M.alloc<unsigned char>(P->factor_elems * rsz);
+  P->lu_scratch = M.alloc<unsigned char>((size_t)L.n_sub * 2 * kLuNB * kLuNB * rsz);
+  P->AT = M.alloc<double2>((size_t)L.nt * nloc * nloc);
+  P->BF = M.alloc<double>(L.ft_face.size() * nfloc * nfloc);
+  P->vals = M.alloc<double2>(L.cols.size());
+  if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->BF || !P->vals) {
+    set_error("device allocation failed (factors or element data)");
+    return MXW_ENOMEM;
+  }
+  {
+    const size_t dyn = 2 * (size_t)L.max_ns;
+    HIP_CHECK(prepare_local_solve(dyn * 8, dyn * 4));
+  }
+  // FP64 element and face matrices, CSR assembly of A
+  {
+    ScopedTimer tm(st, "assemble");
+    launch_element(st, L.nt, P->xyz, P->tets, P->eps, P->phi, P->curl, nloc, L.basis.ncurl_max, L.k0 * L.k0, P->AT);
+    launch_face(st, (int64_t)L.ft_face.size(), P->xyz, P->ft_vert, P->fphi, nfloc, P->BF);
+    AssembleArgs aa{L.ndof, P->rowptr, P->cols, P->dof_ent, P->ent_tet_ptr, P->ent_tets, P->ent_imp_ptr, P->ent_imps,
+                    P->tet_dofs, nloc, P->AT, P->imp_ft, P->imp_beta, P->ft_dofs, nfloc, P->BF, P->vals};
+    launch_assemble_rows(st, aa);
+  }
+  HIP_CHECK(hipGetLastError());
+  const int64_t nnz_row = L.ndof ? L.rowptr.back() / L.ndof : 0;
+  P->spmv_group = nnz_row <= 12 ? 4 : nnz_row <= 24 ? 8 : nnz_row <= 64 ? 16 : 32;
+  if (P->mixed)
+    TRY(build_local_and_factor<float>(P.get(), st, false));
+  else
+    TRY(build_local_and_factor<double>(P.get(), st, false));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (!defer_factor) {
+    mxw_status s = factor_impl(P.get(), st);
+    if (s != MXW_OK && s != MXW_ESINGULAR) return s;
+    if (s == MXW_ESINGULAR) {
+      *out = P.release();
+      return s;
+    }
+  }
+  *out = P.release();
+  return MXW_OK;
+}
+
+void mxw_problem_destroy(mxw_problem* prob) {
+  if (!prob) return;
+  if (prob->kw.host) hipHostFree(prob->kw.host);
+  delete prob;
+}
+
+mxw_status mxw_problem_get_info(const mxw_problem* prob, mxw_layout_info* info) {
+  TRY(check_problem(prob));
+  if (!info) {
+    set_error("info is NULL");
+    return MXW_EINVAL;
+  }
+  fill_info(prob->L, info);
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_factor(mxw_problem* prob, void* stream) {
+  TRY(check_problem(prob));
+  return factor_impl(prob, (hipStream_t)stream);
+}
+
+mxw_status mxw_problem_export_matrix(const mxw_problem* prob, double* vals) {
+  TRY(check_problem(prob));
+  if (!vals) {
+    set_error("vals is NULL");
+    return MXW_EINVAL;
+  }
+  HIP_CHECK(hipDeviceSynchronize());
+  HIP_CHECK(hipMemcpy(vals, prob->vals, prob->L.cols.size() * 16, hipMemcpyDeviceToHost));
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_export_local(const mxw_problem* prob, int32_t s, double* a_s) {
+  TRY(check_problem(prob));
+  if (!a_s || s < 0 || s >= prob->L.n_sub) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  if (prob->factored) {
+    set_error("local matrices are overwritten by their factors");
+    return MXW_EINVAL;
+  }
+  const int64_t n = prob->L.sub_dof_ptr[s + 1] - prob->L.sub_dof_ptr[s];
+  const int64_t ld = prob->h_lds[s];
+  const size_t rsz = prob->mixed ? 4 : 8;
+  std::vector<unsigned char> buf(2 * ld * n * rsz);
+  HIP_CHECK(hipDeviceSynchronize());
+  HIP_CHECK(hipMemcpy(buf.data(), (unsigned char*)prob->F + prob->h_foff[s] * rsz, buf.size(), hipMemcpyDeviceToHost));
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = 0; i < n; ++i) {
+      double re, im;
+      if (prob->mixed) {
+        re = ((float*)buf.data())[j * ld + i];
+        im = ((float*)buf.data())[ld * n + j * ld + i];
+      } else {
+        re = ((double*)buf.data())[j * ld + i];
+        im = ((double*)buf.data())[ld * n + j * ld + i];
+      }
+      a_s[2 * (j * n + i)] = re;
+      a_s[2 * (j * n + i) + 1] = im;
+    }
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev, void* stream) {
+  TRY(check_problem(prob));
+  if (nrhs < 0 || (nrhs > 0 && (!src || !b_dev))) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const Layout& L = prob->L;
+  const int64_t n = L.ndof;
+  double2* b = (double2*)b_dev;
+  HIP_CHECK(hipMemsetAsync(b, 0, sizeof(double2) * n * nrhs, st));
+  double2* work = nullptr;
+  for (int c = 0; c < nrhs; ++c) {
+    const mxw_source& S = src[c];
+    if (S.kind == MXW_SRC_DIPOLE) {
+      // lowest-index element whose barycentric coordinates are all >= -1e-12
+      int64_t found = -1;
+      double lam[4] = {0, 0, 0, 0};
+      for (int64_t t = 0; t < L.nt && found < 0; ++t) {
+        const double* X[4];
+        for (int q = 0; q < 4; ++q) X[q] = &L.xyz[3 * (int64_t)L.tets[4 * t + q]];
+        double J[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc) J[r][cc] = X[cc + 1][r] - X[0][r];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        const double y[3] = {S.pos[0] - X[0][0], S.pos[1] - X[0][1], S.pos[2] - X[0][2]};
+        // Cramer's rule for J xi = y
+        double xi[3];
+        for (int k = 0; k < 3; ++k) {
+          double M[3][3];
+          for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc) M[r][cc] = (cc == k) ? y[r] : J[r][cc];
+          xi[k] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                   M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+        }
+        const double l0 = 1.0 - xi[0] - xi[1] - xi[2];
+        if (l0 >= -1e-12 && xi[0] >= -1e-12 && xi[1] >= -1e-12 && xi[2] >= -1e-12) {
+          found = t;
+          lam[0] = l0;
+          lam[1] = xi[0];
+          lam[2] = xi[1];
+          lam[3] = xi[2];
+        }
+      }
+      if (found < 0) {
+        set_error("dipole position outside the mesh");
+        return MXW_EINVAL;
+      }
+      launch_rhs_dipole(st, prob->xyz, prob->tets, prob->tet_dofs, prob->phi, L.basis.nloc, found, lam, S.pol_re,
+                        S.pol_im, b + (int64_t)c * n);
+    } else if (S.kind == MXW_SRC_PLANEWAVE) {
+      if (!work) {
+        HIP_CHECK(hipMallocAsync((void**)&work, sizeof(double2) * std::max<size_t>(1, L.imp_ft.size() * L.basis.nfloc), st));
+      }
+      PlaneWaveArgs pa{(int)L.imp_ft.size(), n, prob->xyz, prob->ft_vert, prob->imp_ft, prob->imp_opp, prob->imp_beta,
+                       prob->imp_eps, prob->fphi, L.basis.nfloc, L.k0, prob->nq, prob->gx, prob->gw, prob->dof_ent,
+                       prob->ent_imp_ptr, prob->ent_imps, prob->ft_dofs};
+      launch_rhs_planewave(st, pa, S.pol_re, S.pol_im, S.dir, work, b + (int64_t)c * n);
+    } else {
+      set_error("unknown source kind");
+      return MXW_EINVAL;
+    }
+  }
+  HIP_CHECK(hipGetLastError());
+  if (work) HIP_CHECK(hipFreeAsync(work, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_dev, double* y_dev, void* stream) {
+  TRY(check_problem(prob));
+  if (nrhs < 0 || (nrhs > 0 && (!x_dev || !y_dev))) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  spmv_dev(prob, st, (const double2*)x_dev, (double2*)y_dev, nullptr, nrhs, nullptr);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(st));
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double* v_dev, double* z_dev, void* stream) {
+  TRY(check_problem(prob));
+  if (nrhs < 0 || (nrhs > 0 && (!v_dev || !z_dev))) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  if (!prob->factored) {
+    set_error("problem is not factorised");
+    return MXW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  double2* ys = nullptr;
+  if (prob->L.variant == MXW_PREC_OAS) HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
+  apply_prec_dev(prob, st, (const double2*)v_dev, prob->L.ndof, (double2*)z_dev, prob->L.ndof, nrhs, nullptr, ys);
+  HIP_CHECK(hipGetLastError());
+  if (ys) HIP_CHECK(hipFreeAsync(ys, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return MXW_OK;
+}
+
+mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, const mxw_solve_opts* opts, void* stream,
+                         double* x_dev, int32_t* iters_out, double* relres_out) {
+  TRY(check_problem(P));
+  if (nrhs < 1 || !b_dev || !x_dev || !opts) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  if (opts->restart < 1 || opts->restart > 200 || opts->max_iters < 1 || !(opts->tol > 0)) {
+    set_error("invalid solve options (restart 1..200, max_iters >= 1, tol > 0)");
+    return MXW_EINVAL;
+  }
+  if (opts->krylov != MXW_KRYLOV_PSEUDOBLOCK) {
+    set_error("block GMRES is not available in this build");
+    return MXW_EINVAL;
+  }
+  if (!P->factored) {
+    set_error("problem is not factorised");
+    return MXW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int m = opts->restart, maxv = m + 1;
+  const int64_t n = P->L.ndof;
+  TRY(ensure_krylov(P, nrhs, m));
+  KrylovWork& k = P->kw;
+  const double2* B = (const double2*)b_dev;
+  double2* X = (double2*)x_dev;
+  const int64_t vcol = (int64_t)maxv * n, zcol = (int64_t)m * n;
+  double* hbuf = k.host;
+
+  std::vector<double> bnorm(nrhs), beta(nrhs), relres(nrhs, 1.0);
+  std::vector<int> iters(nrhs, 0), conv(nrhs, 0), act(nrhs, 0), jd(nrhs, 0);
+  launch_norm(st, n, B, n, k.npart, k.beta, nrhs, nullptr);
+  HIP_CHECK(hipMemcpyAsync(hbuf, k.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (int c = 0; c < nrhs; ++c) {
+    bnorm[c] = hbuf[c];
+    beta[c] = bnorm[c];
+    if (!(bnorm[c] > 0)) {
+      conv[c] = 1;
+      relres[c] = 0.0;
+    }
+  }
+  HIP_CHECK(hipMemsetAsync(X, 0, sizeof(double2) * n * nrhs, st));
+  HIP_CHECK(hipMemcpyAsync(k.Rv, B, sizeof(double2) * n * nrhs, hipMemcpyDeviceToDevice, st));
+  mxw_status result = MXW_OK;
+  bool breakdown_any = false;
+  while (true) {
+    int nact = 0;
+    for (int c = 0; c < nrhs; ++c) {
+      act[c] = (!conv[c] && iters[c] < opts->max_iters) ? 1 : 0;
+      nact += act[c];
+      jd[c] = 0;
+    }
+    if (nact == 0) break;
+    HIP_CHECK(hipMemcpyAsync(k.active, act.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    // V_0 = r / beta ; g = beta e_1
+    launch_scale_inv(st, n, k.Rv, n, k.V, vcol, k.beta, nrhs, k.active);
+    HIP_CHECK(hipMemsetAsync(k.g, 0, sizeof(double2) * nrhs * (maxv + 1), st));
+    {
+      std::vector<double2> g0((size_t)nrhs * (maxv + 1), make_double2(0.0, 0.0));
+      for (int c = 0; c < nrhs; ++c) g0[(size_t)c * (maxv + 1)] = make_double2(beta[c], 0.0);
+      HIP_CHECK(hipMemcpyAsync(k.g, g0.data(), sizeof(double2) * g0.size(), hipMemcpyHostToDevice, st));
+      HIP_CHECK(hipStreamSynchronize(st));   // g0 lives on the host stack
+    }
+    for (int j = 0; j < m; ++j) {
+      double2* Vj = k.V + (int64_t)j * n;
+      double2* Zj = k.Z + (int64_t)j * n;
+      // z_j = M^{-1} v_j (columns at stride vcol / zcol)
+      apply_prec_dev(P, st, Vj, vcol, Zj, zcol, nrhs, k.active, k.YS);
+      {
+        ScopedTimer tm(st, "spmv");
+        launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, zcol, k.W, n, nullptr, 0, nrhs, k.active);
+      }
+      {
+        ScopedTimer tm(st, "cgs");
+        launch_norm(st, n, k.W, n, k.npart, k.w0, nrhs, k.active);
+        launch_dots(st, n, j + 1, k.V, vcol, k.W, n, k.part, maxv, nrhs, k.active);
+        launch_reduce_dots(st, n, j + 1, k.part, k.h1, maxv, 0, nrhs, k.active);
+        launch_update(st, n, j + 1, k.V, vcol, k.W, n, k.h1, maxv, nrhs, k.active);
+        launch_dots(st, n, j + 1, k.V, vcol, k.W, n, k.part, maxv, nrhs, k.active);
+        launch_reduce_dots(st, n, j + 1, k.part, k.h2, maxv, 0, nrhs, k.active);
+        launch_update(st, n, j + 1, k.V, vcol, k.W, n, k.h2, maxv, nrhs, k.active);
+        launch_reduce_dots(st, n, j + 1, k.part, k.h1, maxv, 1, nrhs, k.active);   // h1 += h2
+        launch_norm(st, n, k.W, n, k.npart, k.hn, nrhs, k.active);
+        launch_givens(st, nrhs, j, maxv, k.h1, k.hn, k.H, m, k.cs, k.sn, k.g, k.est, k.active);
+        launch_scale_inv(st, n, k.W, n, k.V + (int64_t)(j + 1) * n, vcol, k.hn, nrhs, k.active);
+      }
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipMemcpyAsync(hbuf, k.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipMemcpyAsync(hbuf + nrhs, k.hn, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipMemcpyAsync(hbuf + 2 * nrhs, k.w0, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      int still = 0;
+      bool changed = false;
+      for (int c = 0; c < nrhs; ++c) {
+        if (!act[c]) continue;
+        iters[c]++;
+        jd[c] = j + 1;
+        const double est = hbuf[c], hn = hbuf[nrhs + c], w0 = hbuf[2 * nrhs + c];
+        const bool brk = !(hn > 1e-14 * w0);
+        if (brk) breakdown_any = true;
+        if (est <= opts->tol * bnorm[c] || brk || iters[c] >= opts->max_iters || !std::isfinite(est)) {
+          act[c] = 0;
+          changed = true;
+        } else {
+          ++still;
+        }
+      }
+      if (still == 0) break;
+      if (changed) HIP_CHECK(hipMemcpyAsync(k.active, act.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+      if (changed) HIP_CHECK(hipStreamSynchronize(st));
+    }
+    // x += Z y; r = b - A x
+    HIP_CHECK(hipMemcpyAsync(k.jd, jd.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    launch_backsolve(st, nrhs, k.jd, maxv, k.H, m, k.g, k.y);
+    launch_xupdate(st, n, k.jd, k.Z, zcol, k.y, maxv, X, n, nrhs);
+    spmv_dev(P, st, X, k.Rv, B, nrhs, nullptr);
+    launch_norm(st, n, k.Rv, n, k.npart, k.beta, nrhs, nullptr);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(hbuf, k.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int c = 0; c < nrhs; ++c) {
+      if (conv[c]) continue;
+      beta[c] = hbuf[c];
+      relres[c] = beta[c] / bnorm[c];
+      if (relres[c] <= opts->tol) conv[c] = 1;
+    }
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c)
+      if (!conv[c] && iters[c] < opts->max_iters && std::isfinite(relres[c])) any = true;
+    if (!any) break;
+  }
+  for (int c = 0; c < nrhs; ++c) {
+    if (iters_out) iters_out[c] = iters[c];
+    if (relres_out) relres_out[c] = relres[c];
+    if (!conv[c]) result = breakdown_any ? MXW_EBREAKDOWN : MXW_ENOTCONV;
+  }
+  if (result == MXW_ENOTCONV) set_error("max_iters reached before the tolerance");
+  if (result == MXW_EBREAKDOWN) set_error("Krylov breakdown before the tolerance");
+  return result;
+}
+
+mxw_status mxw_solve(mxw_problem* P, int32_t nrhs, const mxw_source* src, const mxw_solve_opts* opts, void* stream,
+                     double* E_out, int32_t E_out_is_device, int32_t* iters_out, double* relres_out) {
+  TRY(check_problem(P));
+  if (nrhs < 1 || !src || !opts || !E_out) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = P->L.ndof;
+  double2 *b = nullptr, *x = nullptr;
+  HIP_CHECK(hipMalloc((void**)&b, sizeof(double2) * n * nrhs));
+  if (E_out_is_device)
+    x = (double2*)E_out;
+  else if (hipMalloc((void**)&x, sizeof(double2) * n * nrhs) != hipSuccess) {
+    hipFree(b);
+    set_error("device allocation failed");
+    return MXW_ENOMEM;
+  }
+  mxw_status s = mxw_problem_rhs(P, nrhs, src, (double*)b, stream);
+  if (s == MXW_OK || s == MXW_ENOTCONV) s = mxw_solve_rhs(P, nrhs, (double*)b, opts, stream, (double*)x, iters_out, relres_out);
+  if (!E_out_is_device && (s == MXW_OK || s == MXW_ENOTCONV || s == MXW_EBREAKDOWN)) {
+    hipMemcpyAsync(E_out, x, sizeof(double2) * n * nrhs, hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+  }
+  hipFree(b);
+  if (!E_out_is_device) hipFree(x);
+  return s;
+}
+
+mxw_status mxw_set_timing(int32_t enabled) {
+  g_timing = enabled != 0;
+  return MXW_OK;
+}
+
+mxw_status mxw_get_timing(const char* name, double* total_ms, int64_t* launches) {
+  if (!name || !total_ms || !launches) {
+    set_error("NULL argument");
+    return MXW_EINVAL;
+  }
+  flush_timing();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  auto it = g_totals.find(name);
+  *total_ms = it == g_totals.end() ? 0.0 : it->second.first;
+  *launches = it == g_totals.end() ? 0 : it->second.second;
+  return MXW_OK;
+}
+
+mxw_status mxw_reset_timing(void) {
+  flush_timing();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_totals.clear();
+  return MXW_OK;
+}
+
+}  // extern "C"

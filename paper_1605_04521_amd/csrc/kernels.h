@@ -1,0 +1,132 @@
+// Kernel launchers (host-callable) of the mxw library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mxw_internal.h"
+
+namespace mxw {
+
+constexpr int kLuNB = 32;   // LU panel width = block size of the triangular sweeps
+
+void launch_element(hipStream_t st, int64_t nt, const double* xyz, const int* tets, const double* eps,
+                    const Term* phi, const Term* curl, int nloc, int ncurl, double k0sq, double2* AT);
+void launch_face(hipStream_t st, int64_t nft, const double* xyz, const int* fvert, const Term* fphi, int nfloc,
+                 double* BF);
+
+struct AssembleArgs {
+  int64_t ndof;
+  const int64_t* rowptr;
+  const int* cols;
+  const int* dof_ent;
+  const int64_t* ent_tet_ptr;
+  const int* ent_tets;
+  const int64_t* ent_imp_ptr;
+  const int* ent_imps;
+  const int* tet_dofs;
+  int nloc;
+  const double2* AT;
+  const int* imp_ft;
+  const double* imp_beta;
+  const int* ft_dofs;
+  int nfloc;
+  const double* BF;
+  double2* vals;
+};
+void launch_assemble_rows(hipStream_t st, const AssembleArgs& a);
+
+struct LocalAssembleArgs {
+  int n_sub;
+  const int64_t* foff;
+  const int* nsz;
+  const int* lds;
+  const int64_t* tet_ptr;
+  const int* tets;
+  const int* lmap;
+  const double2* AT;
+  int nloc;
+  const int64_t* face_ptr;
+  const int* face_ft;
+  const double* face_coef;
+  const int* face_lmap;
+  const double* BF;
+  int nfloc;
+};
+template <typename R>
+void launch_assemble_local(hipStream_t st, const LocalAssembleArgs& a, R* F);
+
+void launch_rhs_dipole(hipStream_t st, const double* xyz, const int* tets, const int* tet_dofs, const Term* phi,
+                       int nloc, int64_t t, const double lam[4], const double pr[3], const double pi[3],
+                       double2* b);
+
+struct PlaneWaveArgs {
+  int nimp;
+  int64_t ndof;
+  const double* xyz;
+  const int* fvert;
+  const int* imp_ft;
+  const int* imp_opp;
+  const double* imp_beta;
+  const double* imp_eps;
+  const Term* fphi;
+  int nfloc;
+  double k0;
+  int nq;
+  const double* gx;
+  const double* gw;
+  const int* dof_ent;
+  const int64_t* ent_imp_ptr;
+  const int* ent_imps;
+  const int* ft_dofs;
+};
+void launch_rhs_planewave(hipStream_t st, const PlaneWaveArgs& a, const double pr[3], const double pi[3],
+                          const double d[3], double2* work, double2* b);
+
+template <typename R>
+void launch_lu(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds, int* perm,
+               const int64_t* poff, R* scratch, int* info, const int* order);
+
+struct LocalSolveArgs {
+  int n_sub;
+  int max_ns;
+  const int64_t* foff;
+  const int* nsz;
+  const int* lds;
+  const int* perm;
+  const int64_t* poff;
+  const int* sub_dofs;
+  const uint8_t* pou;
+  const int* order;
+};
+template <typename R>
+void launch_local_solve(hipStream_t st, const LocalSolveArgs& a, const R* F, const double2* v, int64_t vstride,
+                        double2* z, int64_t zstride, double2* ys, int64_t ystride, int ncol, const int* active);
+hipError_t prepare_local_solve(size_t dyn_bytes_double, size_t dyn_bytes_float);
+void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const int64_t* pos, const double2* ys,
+                       int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active);
+
+void launch_spmv(hipStream_t st, int group, int64_t n, const int64_t* rowptr, const int* cols, const double2* vals,
+                 const double2* x, int64_t xstride, double2* y, int64_t ystride, const double2* b, int64_t bstride,
+                 int ncol, const int* active);
+
+int red_blocks(int64_t ndof);
+void launch_dots(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64_t vcol, const double2* w,
+                 int64_t wcol, double2* part, int maxv, int ncol, const int* active);
+void launch_reduce_dots(hipStream_t st, int64_t ndof, int nvec, const double2* part, double2* h, int maxv,
+                        int accumulate, int ncol, const int* active);
+void launch_update(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64_t vcol, double2* w, int64_t wcol,
+                   const double2* hpass, int maxv, int ncol, const int* active);
+void launch_norm(hipStream_t st, int64_t ndof, const double2* w, int64_t wcol, double* part, double* out, int ncol,
+                 const int* active);
+void launch_scale_inv(hipStream_t st, int64_t ndof, const double2* x, int64_t xcol, double2* y, int64_t ycol,
+                      const double* norm, int ncol, const int* active);
+void launch_givens(hipStream_t st, int ncol, int j, int maxv, const double2* h, const double* hn, double2* H, int ldh,
+                   double* cs, double2* sn, double2* g, double* est, const int* active);
+void launch_backsolve(hipStream_t st, int ncol, const int* jd, int maxv, const double2* H, int ldh, const double2* g,
+                      double2* y);
+void launch_xupdate(hipStream_t st, int64_t ndof, const int* jd, const double2* Z, int64_t zcol, const double2* y,
+                    int maxv, double2* x, int64_t xcol, int ncol);
+
+}  // namespace mxw

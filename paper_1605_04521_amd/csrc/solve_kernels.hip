@@ -1,0 +1,553 @@
+// Per-iteration kernels of preconditioned GMRES (Sec. 4-5):
+//   * fused ORAS application: restriction R_s v, row permutation, forward and
+//     backward sweeps with the LU factors, Boolean prolongation R_s^T D_s;
+//   * complex CSR SpMV (FP64);
+//   * classical Gram-Schmidt with reorthogonalisation (two passes) using
+//     block partial sums reduced in a fixed order (deterministic);
+//   * complex Givens updates of the Hessenberg least-squares problem, the
+//     triangular solve for y and the update x += Z y.
+// Several right-hand sides run in the same launches (grid dimension y); every
+// column keeps its own Krylov space (the pseudo-block scheme of Sec. 5).
+#include "device.h"
+#include "kernels.h"
+
+namespace mxw {
+
+// ---------------------------------------------------------------------------
+// ORAS application, one workgroup per (subdomain, column)
+// ---------------------------------------------------------------------------
+template <typename R, int NB>
+__global__ void __launch_bounds__(256) k_local_solve(const R* __restrict__ F, const int64_t* __restrict__ foff,
+                                                     const int* __restrict__ nsz, const int* __restrict__ lds,
+                                                     const int* __restrict__ perm, const int64_t* __restrict__ poff,
+                                                     const int* __restrict__ sub_dofs, const uint8_t* __restrict__ pou,
+                                                     const double2* __restrict__ v, int64_t vstride,
+                                                     double2* __restrict__ z, int64_t zstride,
+                                                     double2* __restrict__ ys, int64_t ystride,
+                                                     const int* __restrict__ active, const int* __restrict__ order) {
+  extern __shared__ unsigned char dyn[];
+  __shared__ R pr_[8][NB], pi_[8][NB];
+  __shared__ R ar_[NB], ai_[NB];
+  const int s = order ? order[blockIdx.x] : blockIdx.x;
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int n = nsz[s];
+  const int64_t ld = lds[s];
+  const R* Ar = F + foff[s];
+  const R* Ai = Ar + ld * n;
+  const int* P = perm + poff[s];
+  const int* D = sub_dofs + poff[s];
+  R* xr = reinterpret_cast<R*>(dyn);
+  R* xi = xr + n;
+  const double2* vc = v + (int64_t)col * vstride;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += 256) {
+    const double2 a = vc[D[P[i]]];
+    xr[i] = (R)a.x;
+    xi[i] = (R)a.y;
+  }
+  __syncthreads();
+  const int r = tid % NB, cg = tid / NB;   // NB rows x (256/NB) column groups
+  constexpr int CG = 256 / NB;
+  // forward sweep with unit-lower L; diagonal blocks hold L_kk^{-1}
+  for (int b0 = 0; b0 < n; b0 += NB) {
+    const int bn = min(NB, n - b0);
+    R s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+    if (r < bn) {
+      const R* cr = Ar + b0 + r;
+      const R* ci = Ai + b0 + r;
+      int c = cg;
+      for (; c + CG < b0; c += 2 * CG) {
+        const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
+        const R l1r = cr[(int64_t)(c + CG) * ld], l1i = ci[(int64_t)(c + CG) * ld];
+        const R x0r = xr[c], x0i = xi[c], x1r = xr[c + CG], x1i = xi[c + CG];
+        s0r += l0r * x0r - l0i * x0i;
+        s0i += l0r * x0i + l0i * x0r;
+        s1r += l1r * x1r - l1i * x1i;
+        s1i += l1r * x1i + l1i * x1r;
+      }
+      for (; c < b0; c += CG) {
+        const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
+        s0r += l0r * xr[c] - l0i * xi[c];
+        s0i += l0r * xi[c] + l0i * xr[c];
+      }
+    }
+    pr_[cg][r] = s0r + s1r;
+    pi_[cg][r] = s0i + s1i;
+    __syncthreads();
+    if (tid < bn) {
+      R tr = xr[b0 + tid], ti = xi[b0 + tid];
+      for (int q = 0; q < CG; ++q) {
+        tr -= pr_[q][tid];
+        ti -= pi_[q][tid];
+      }
+      ar_[tid] = tr;
+      ai_[tid] = ti;
+    }
+    __syncthreads();
+    R tr = 0, ti = 0;
+    if (r < bn) {
+      for (int c = cg; c < r; c += CG) {
+        const int64_t o = (int64_t)(b0 + c) * ld + b0 + r;
+        const R lr = Ar[o], li = Ai[o];
+        tr += lr * ar_[c] - li * ai_[c];
+        ti += lr * ai_[c] + li * ar_[c];
+      }
+    }
+    pr_[cg][r] = tr;
+    pi_[cg][r] = ti;
+    __syncthreads();
+    if (tid < bn) {
+      R yr = ar_[tid], yi = ai_[tid];
+      for (int q = 0; q < CG; ++q) {
+        yr += pr_[q][tid];
+        yi += pi_[q][tid];
+      }
+      xr[b0 + tid] = yr;
+      xi[b0 + tid] = yi;
+    }
+    __syncthreads();
+  }
+  // backward sweep with U; diagonal blocks hold U_kk^{-1}
+  const int last = ((n - 1) / NB) * NB;
+  for (int b0 = last; b0 >= 0; b0 -= NB) {
+    const int bn = min(NB, n - b0);
+    R s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+    if (r < bn) {
+      const R* cr = Ar + b0 + r;
+      const R* ci = Ai + b0 + r;
+      int c = b0 + bn + cg;
+      for (; c + CG < n; c += 2 * CG) {
+        const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
+        const R l1r = cr[(int64_t)(c + CG) * ld], l1i = ci[(int64_t)(c + CG) * ld];
+        const R x0r = xr[c], x0i = xi[c], x1r = xr[c + CG], x1i = xi[c + CG];
+        s0r += l0r * x0r - l0i * x0i;
+        s0i += l0r * x0i + l0i * x0r;
+        s1r += l1r * x1r - l1i * x1i;
+        s1i += l1r * x1i + l1i * x1r;
+      }
+      for (; c < n; c += CG) {
+        const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
+        s0r += l0r * xr[c] - l0i * xi[c];
+        s0i += l0r * xi[c] + l0i * xr[c];
+      }
+    }
+    pr_[cg][r] = s0r + s1r;
+    pi_[cg][r] = s0i + s1i;
+    __syncthreads();
+    if (tid < bn) {
+      R tr = xr[b0 + tid], ti = xi[b0 + tid];
+      for (int q = 0; q < CG; ++q) {
+        tr -= pr_[q][tid];
+        ti -= pi_[q][tid];
+      }
+      ar_[tid] = tr;
+      ai_[tid] = ti;
+    }
+    __syncthreads();
+    R tr = 0, ti = 0;
+    if (r < bn) {
+      for (int c = r + cg; c < bn; c += CG) {
+        const int64_t o = (int64_t)(b0 + c) * ld + b0 + r;
+        const R ur = Ar[o], ui = Ai[o];
+        tr += ur * ar_[c] - ui * ai_[c];
+        ti += ur * ai_[c] + ui * ar_[c];
+      }
+    }
+    pr_[cg][r] = tr;
+    pi_[cg][r] = ti;
+    __syncthreads();
+    if (tid < bn) {
+      R yr = 0, yi = 0;
+      for (int q = 0; q < CG; ++q) {
+        yr += pr_[q][tid];
+        yi += pi_[q][tid];
+      }
+      xr[b0 + tid] = yr;
+      xi[b0 + tid] = yi;
+    }
+    __syncthreads();
+  }
+  // prolongation: Boolean partition of unity -> each global unknown is
+  // written by its owner only; without weights (OAS) the local results go
+  // to a buffer that a gather sums in a fixed order
+  if (ys) {
+    double2* yc = ys + (int64_t)col * ystride + poff[s];
+    for (int i = tid; i < n; i += 256) yc[i] = make_double2((double)xr[i], (double)xi[i]);
+  } else {
+    double2* zc = z + (int64_t)col * zstride;
+    const uint8_t* w = pou + poff[s];
+    for (int i = tid; i < n; i += 256)
+      if (w[i]) zc[D[i]] = make_double2((double)xr[i], (double)xi[i]);
+  }
+}
+
+// z[i] = sum over the subdomains containing i of y_s (fixed order)
+__global__ void k_gather_all(int64_t ndof, const int64_t* __restrict__ ptr, const int64_t* __restrict__ pos,
+                             const double2* __restrict__ ys, int64_t ystride, double2* __restrict__ z,
+                             int64_t zstride, const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndof) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) acc = cadd(acc, ys[(int64_t)col * ystride + pos[q]]);
+  z[(int64_t)col * zstride + i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// SpMV: y = A x (or y = b - A x), G lanes per row
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t* __restrict__ rowptr, const int* __restrict__ cols,
+                                              const double2* __restrict__ vals, const double2* __restrict__ x,
+                                              int64_t xstride, double2* __restrict__ y, int64_t ystride,
+                                              const double2* __restrict__ b, int64_t bstride,
+                                              const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x % G;
+  if (row >= n) return;
+  const double2* xc = x + (int64_t)col * xstride;
+  double sr = 0.0, si = 0.0;
+  const int64_t r0 = rowptr[row], r1 = rowptr[row + 1];
+  for (int64_t c = r0 + l; c < r1; c += G) {
+    const double2 a = vals[c];
+    const double2 xv = xc[cols[c]];
+    sr += a.x * xv.x - a.y * xv.y;
+    si += a.x * xv.y + a.y * xv.x;
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    sr += __shfl_xor(sr, o, G);
+    si += __shfl_xor(si, o, G);
+  }
+  if (l == 0) {
+    if (b) {
+      const double2 bv = b[(int64_t)col * bstride + row];
+      y[(int64_t)col * ystride + row] = make_double2(bv.x - sr, bv.y - si);
+    } else {
+      y[(int64_t)col * ystride + row] = make_double2(sr, si);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector kernels.  Column c of the batch uses V + c*vcol, where
+// vector i of the basis is at offset i*ndof.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 2048;       // elements per block in reductions
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
+  return t;
+}
+
+// part[col][blk][i] = sum_{k in blk} conj(V_i[k]) w[k], i = 0..j
+__global__ void __launch_bounds__(kRedThreads) k_dots(int64_t ndof, int nvec, const double2* __restrict__ V,
+                                                      int64_t vcol, const double2* __restrict__ w, int64_t wcol,
+                                                      double2* __restrict__ part, int nblk, int maxv,
+                                                      const int* __restrict__ active) {
+  __shared__ double sh[8];
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t k0 = (int64_t)blockIdx.x * kChunk;
+  double2 wl[kChunk / kRedThreads];
+#pragma unroll
+  for (int q = 0; q < kChunk / kRedThreads; ++q) {
+    const int64_t k = k0 + threadIdx.x + q * kRedThreads;
+    wl[q] = k < ndof ? w[(int64_t)col * wcol + k] : make_double2(0.0, 0.0);
+  }
+  for (int i = 0; i < nvec; ++i) {
+    const double2* vi = V + (int64_t)col * vcol + (int64_t)i * ndof;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int q = 0; q < kChunk / kRedThreads; ++q) {
+      const int64_t k = k0 + threadIdx.x + q * kRedThreads;
+      if (k < ndof) {
+        const double2 a = vi[k];
+        sr += a.x * wl[q].x + a.y * wl[q].y;
+        si += a.x * wl[q].y - a.y * wl[q].x;
+      }
+    }
+    sr = block_sum(sr, sh);
+    si = block_sum(si, sh);
+    if (threadIdx.x == 0) part[((int64_t)col * nblk + blockIdx.x) * maxv + i] = make_double2(sr, si);
+  }
+}
+
+// h[col][i] (+)= sum_blk part[col][blk][i]   (fixed order)
+__global__ void k_reduce_dots(int nvec, int nblk, int maxv, const double2* __restrict__ part, double2* __restrict__ h,
+                              int accumulate, const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+    double2 a = make_double2(0.0, 0.0);
+    for (int b = 0; b < nblk; ++b) a = cadd(a, part[((int64_t)col * nblk + b) * maxv + i]);
+    if (accumulate)
+      h[(int64_t)col * maxv + i] = cadd(h[(int64_t)col * maxv + i], a);
+    else
+      h[(int64_t)col * maxv + i] = a;
+  }
+}
+
+// w -= sum_i V_i hpass[i]
+__global__ void k_update(int64_t ndof, int nvec, const double2* __restrict__ V, int64_t vcol, double2* __restrict__ w,
+                         int64_t wcol, const double2* __restrict__ hpass, int maxv, const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  __shared__ double2 hs[256];
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) hs[i] = hpass[(int64_t)col * maxv + i];
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ndof) return;
+  double2 acc = w[(int64_t)col * wcol + k];
+  for (int i = 0; i < nvec; ++i) {
+    const double2 a = V[(int64_t)col * vcol + (int64_t)i * ndof + k];
+    acc.x -= a.x * hs[i].x - a.y * hs[i].y;
+    acc.y -= a.x * hs[i].y + a.y * hs[i].x;
+  }
+  w[(int64_t)col * wcol + k] = acc;
+}
+
+// part[col][blk] = sum |w|^2 over the block
+__global__ void __launch_bounds__(kRedThreads) k_norm2(int64_t ndof, const double2* __restrict__ w, int64_t wcol,
+                                                       double* __restrict__ part, int nblk,
+                                                       const int* __restrict__ active) {
+  __shared__ double sh[8];
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t k0 = (int64_t)blockIdx.x * kChunk;
+  double s = 0.0;
+  for (int q = 0; q < kChunk / kRedThreads; ++q) {
+    const int64_t k = k0 + threadIdx.x + q * kRedThreads;
+    if (k < ndof) {
+      const double2 a = w[(int64_t)col * wcol + k];
+      s += a.x * a.x + a.y * a.y;
+    }
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(int64_t)col * nblk + blockIdx.x] = s;
+}
+
+__global__ void k_reduce_norm(int nblk, const double* __restrict__ part, double* __restrict__ out,
+                              const int* __restrict__ active) {
+  const int col = blockIdx.x;
+  if (active && !active[col]) return;
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int b = 0; b < nblk; ++b) a += part[(int64_t)col * nblk + b];
+    out[col] = sqrt(a);
+  }
+}
+
+// y = alpha * x  (alpha = 1 / norm[col])
+__global__ void k_scale_inv(int64_t ndof, const double2* __restrict__ x, int64_t xcol, double2* __restrict__ y,
+                            int64_t ycol, const double* __restrict__ norm, const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ndof) return;
+  const double nv = norm[col];
+  const double a = nv > 0.0 ? 1.0 / nv : 0.0;
+  const double2 v = x[(int64_t)col * xcol + k];
+  y[(int64_t)col * ycol + k] = make_double2(a * v.x, a * v.y);
+}
+
+// Arnoldi step j, one thread per column: H(:,j) = h (sum of both passes),
+// H(j+1,j) = ||w||; apply the previous rotations, form the new one, update g.
+// est[col] = |g_{j+1}|.
+__global__ void k_givens(int ncol, int j, int maxv, const double2* __restrict__ h, const double* __restrict__ hn,
+                         double2* __restrict__ H, int ldh, double* __restrict__ cs, double2* __restrict__ sn,
+                         double2* __restrict__ g, double* __restrict__ est, const int* __restrict__ active) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  if (active && !active[col]) return;
+  double2* Hc = H + (int64_t)col * ldh * maxv;      // column-major (maxv rows)
+  double* csc = cs + (int64_t)col * maxv;
+  double2* snc = sn + (int64_t)col * maxv;
+  double2* gc = g + (int64_t)col * (maxv + 1);
+  double2* hj = Hc + (int64_t)j * maxv;
+  for (int i = 0; i <= j; ++i) hj[i] = h[(int64_t)col * maxv + i];
+  hj[j + 1] = make_double2(hn[col], 0.0);
+  for (int i = 0; i < j; ++i) {   // [c s; -conj(s) c]
+    const double c = csc[i];
+    const double2 s = snc[i];
+    const double2 a = hj[i], b = hj[i + 1];
+    const double2 t = cadd(make_double2(c * a.x, c * a.y), cmul(s, b));
+    const double2 u = csub(make_double2(c * b.x, c * b.y), cmul(make_double2(s.x, -s.y), a));
+    hj[i] = t;
+    hj[i + 1] = u;
+  }
+  const double2 a = hj[j], b = hj[j + 1];
+  const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+  double c;
+  double2 s;
+  if (nb == 0.0) {
+    c = 1.0;
+    s = make_double2(0.0, 0.0);
+  } else if (na == 0.0) {
+    c = 0.0;
+    s = make_double2(b.x / nb, -b.y / nb);
+  } else {
+    const double nu = hypot(na, nb);
+    c = na / nu;
+    const double2 ph = make_double2(a.x / na, a.y / na);
+    s = cmul(ph, make_double2(b.x / nu, -b.y / nu));
+  }
+  csc[j] = c;
+  snc[j] = s;
+  hj[j] = cadd(make_double2(c * a.x, c * a.y), cmul(s, b));
+  hj[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = gc[j];
+  gc[j + 1] = cmul(make_double2(-s.x, s.y), gj);   // -conj(s) g_j
+  gc[j] = make_double2(c * gj.x, c * gj.y);
+  est[col] = hypot(gc[j + 1].x, gc[j + 1].y);
+}
+
+// y = R^{-1} g (upper triangular, jd x jd), one thread per column
+__global__ void k_backsolve(int ncol, const int* __restrict__ jd, int maxv, const double2* __restrict__ H, int ldh,
+                            const double2* __restrict__ g, double2* __restrict__ y) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  const int n = jd[col];
+  const double2* Hc = H + (int64_t)col * ldh * maxv;
+  const double2* gc = g + (int64_t)col * (maxv + 1);
+  double2* yc = y + (int64_t)col * maxv;
+  for (int i = n - 1; i >= 0; --i) {
+    double2 t = gc[i];
+    for (int q = i + 1; q < n; ++q) t = csub(t, cmul(Hc[(int64_t)q * maxv + i], yc[q]));
+    const double2 d = Hc[(int64_t)i * maxv + i];
+    const double den = d.x * d.x + d.y * d.y;
+    yc[i] = make_double2((t.x * d.x + t.y * d.y) / den, (t.y * d.x - t.x * d.y) / den);
+  }
+}
+
+// x += sum_{i<jd} Z_i y_i
+__global__ void k_xupdate(int64_t ndof, const int* __restrict__ jd, const double2* __restrict__ Z, int64_t zcol,
+                          const double2* __restrict__ y, int maxv, double2* __restrict__ x, int64_t xcol) {
+  const int col = blockIdx.y;
+  const int n = jd[col];
+  if (n == 0) return;
+  __shared__ double2 ys[256];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ys[i] = y[(int64_t)col * maxv + i];
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ndof) return;
+  double2 acc = x[(int64_t)col * xcol + k];
+  for (int i = 0; i < n; ++i) acc = cadd(acc, cmul(Z[(int64_t)col * zcol + (int64_t)i * ndof + k], ys[i]));
+  x[(int64_t)col * xcol + k] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename R>
+void launch_local_solve(hipStream_t st, const LocalSolveArgs& a, const R* F, const double2* v, int64_t vstride,
+                        double2* z, int64_t zstride, double2* ys, int64_t ystride, int ncol, const int* active) {
+  if (a.n_sub == 0 || ncol == 0) return;
+  const size_t dyn = 2 * sizeof(R) * (size_t)a.max_ns;
+  hipLaunchKernelGGL((k_local_solve<R, kLuNB>), dim3(a.n_sub, ncol), dim3(256), dyn, st, F, a.foff, a.nsz, a.lds,
+                     a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, ys, ystride, active, a.order);
+}
+template void launch_local_solve<double>(hipStream_t, const LocalSolveArgs&, const double*, const double2*, int64_t,
+                                         double2*, int64_t, double2*, int64_t, int, const int*);
+template void launch_local_solve<float>(hipStream_t, const LocalSolveArgs&, const float*, const double2*, int64_t,
+                                        double2*, int64_t, double2*, int64_t, int, const int*);
+
+hipError_t prepare_local_solve(size_t dyn_bytes_double, size_t dyn_bytes_float) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_local_solve<double, kLuNB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes_double);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_local_solve<float, kLuNB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)dyn_bytes_float);
+}
+
+void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const int64_t* pos, const double2* ys,
+                       int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active) {
+  if (ndof == 0 || ncol == 0) return;
+  hipLaunchKernelGGL(k_gather_all, dim3((unsigned)((ndof + 255) / 256), ncol), dim3(256), 0, st, ndof, ptr, pos, ys,
+                     ystride, z, zstride, active);
+}
+
+void launch_spmv(hipStream_t st, int group, int64_t n, const int64_t* rowptr, const int* cols, const double2* vals,
+                 const double2* x, int64_t xstride, double2* y, int64_t ystride, const double2* b, int64_t bstride,
+                 int ncol, const int* active) {
+  if (n == 0 || ncol == 0) return;
+  const unsigned nb = (unsigned)((n * group + 255) / 256);
+  switch (group) {
+    case 4:
+      hipLaunchKernelGGL(k_spmv<4>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_spmv<8>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_spmv<16>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      break;
+    default:
+      hipLaunchKernelGGL(k_spmv<32>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      break;
+  }
+}
+
+int red_blocks(int64_t ndof) { return (int)((ndof + kChunk - 1) / kChunk); }
+
+void launch_dots(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64_t vcol, const double2* w,
+                 int64_t wcol, double2* part, int maxv, int ncol, const int* active) {
+  const int nb = red_blocks(ndof);
+  hipLaunchKernelGGL(k_dots, dim3(nb, ncol), dim3(kRedThreads), 0, st, ndof, nvec, V, vcol, w, wcol, part, nb, maxv,
+                     active);
+}
+
+void launch_reduce_dots(hipStream_t st, int64_t ndof, int nvec, const double2* part, double2* h, int maxv,
+                        int accumulate, int ncol, const int* active) {
+  hipLaunchKernelGGL(k_reduce_dots, dim3(1, ncol), dim3(64), 0, st, nvec, red_blocks(ndof), maxv, part, h, accumulate,
+                     active);
+}
+
+void launch_update(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64_t vcol, double2* w, int64_t wcol,
+                   const double2* hpass, int maxv, int ncol, const int* active) {
+  hipLaunchKernelGGL(k_update, dim3((unsigned)((ndof + 255) / 256), ncol), dim3(256), 0, st, ndof, nvec, V, vcol, w,
+                     wcol, hpass, maxv, active);
+}
+
+void launch_norm(hipStream_t st, int64_t ndof, const double2* w, int64_t wcol, double* part, double* out, int ncol,
+                 const int* active) {
+  const int nb = red_blocks(ndof);
+  hipLaunchKernelGGL(k_norm2, dim3(nb, ncol), dim3(kRedThreads), 0, st, ndof, w, wcol, part, nb, active);
+  hipLaunchKernelGGL(k_reduce_norm, dim3(ncol), dim3(64), 0, st, nb, part, out, active);
+}
+
+void launch_scale_inv(hipStream_t st, int64_t ndof, const double2* x, int64_t xcol, double2* y, int64_t ycol,
+                      const double* norm, int ncol, const int* active) {
+  hipLaunchKernelGGL(k_scale_inv, dim3((unsigned)((ndof + 255) / 256), ncol), dim3(256), 0, st, ndof, x, xcol, y, ycol,
+                     norm, active);
+}
+
+void launch_givens(hipStream_t st, int ncol, int j, int maxv, const double2* h, const double* hn, double2* H, int ldh,
+                   double* cs, double2* sn, double2* g, double* est, const int* active) {
+  hipLaunchKernelGGL(k_givens, dim3((ncol + 63) / 64), dim3(64), 0, st, ncol, j, maxv, h, hn, H, ldh, cs, sn, g, est,
+                     active);
+}
+
+void launch_backsolve(hipStream_t st, int ncol, const int* jd, int maxv, const double2* H, int ldh, const double2* g,
+                      double2* y) {
+  hipLaunchKernelGGL(k_backsolve, dim3((ncol + 63) / 64), dim3(64), 0, st, ncol, jd, maxv, H, ldh, g, y);
+}
+
+void launch_xupdate(hipStream_t st, int64_t ndof, const int* jd, const double2* Z, int64_t zcol, const double2* y,
+                    int maxv, double2* x, int64_t xcol, int ncol) {
+  hipLaunchKernelGGL(k_xupdate, dim3((unsigned)((ndof + 255) / 256), ncol), dim3(256), 0, st, ndof, jd, Z, zcol, y,
+                     maxv, x, xcol);
+}
+
+}  // namespace mxw
