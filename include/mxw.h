@@ -162,6 +162,16 @@ mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int
  * it with MXW_ENOMEM before allocating. */
 mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64_t hbm_budget,
                               int32_t defer_factor, mxw_problem** out);
+/* Device problem on the mesh, degree and partition of an existing layout,
+ * with a permittivity field eps [n_tets][2] (NULL = the layout's) and a
+ * wavenumber k0 (negative = the layout's).  The layout's device copy
+ * (geometry, unknown numbering, subdomain maps, face matrices) is built on
+ * first use and shared by every problem created from it; each problem keeps
+ * its layout alive, so the layout handle may be destroyed at any time.  This
+ * is the call for streams of solves on one mesh with changing media. */
+mxw_status mxw_problem_create_from_layout(const mxw_layout* layout, const double* eps, double k0,
+                                          int32_t precision, int32_t prec_variant, void* stream,
+                                          uint64_t hbm_budget, int32_t defer_factor, mxw_problem** out);
 void mxw_problem_destroy(mxw_problem* prob);
 mxw_status mxw_problem_get_info(const mxw_problem* prob, mxw_layout_info* info);
 /* Factorises every A_s in place (batched LU, partial pivoting). Idempotent.
@@ -198,6 +208,12 @@ mxw_status mxw_solve(mxw_problem* prob, int32_t nrhs, const mxw_source* src,
 mxw_status mxw_solve_rhs(mxw_problem* prob, int32_t nrhs, const double* b_dev,
                          const mxw_solve_opts* opts, void* stream, double* x_dev,
                          int32_t* iters_out, double* relres_out);
+
+/* Residual estimates |g_{j+1}| / ||b|| of every Arnoldi step of column col
+ * in the last solve on this problem (host array; len receives the count,
+ * at most max_len values are written; out may be NULL). */
+mxw_status mxw_solve_history(const mxw_problem* prob, int32_t col, double* out, int32_t max_len,
+                             int32_t* len);
 
 /* ---- instrumentation --------------------------------------------------- */
 

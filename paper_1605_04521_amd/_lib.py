@@ -86,6 +86,8 @@ _SIGS = {
                                          C.POINTER(C.c_uint64)]),
     "mxw_problem_create": (C.c_int32, [C.POINTER(ProblemDesc), C.c_void_p, C.c_uint64, C.c_int32,
                                        C.POINTER(C.c_void_p)]),
+    "mxw_problem_create_from_layout": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
+                                                   C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
     "mxw_problem_destroy": (None, [C.c_void_p]),
     "mxw_problem_get_info": (C.c_int32, [C.c_void_p, C.POINTER(LayoutInfo)]),
     "mxw_problem_factor": (C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -98,6 +100,7 @@ _SIGS = {
                               C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mxw_solve_rhs": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(SolveOpts), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mxw_solve_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "mxw_set_timing": (C.c_int32, [C.c_int32]),
     "mxw_get_timing": (C.c_int32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "mxw_reset_timing": (C.c_int32, []),

@@ -73,18 +73,40 @@ def _stream():
 class Problem:
     """Device operator: assembled A, local matrices, batched LU factors."""
 
-    def __init__(self, desc: B.Desc, hbm_budget: int = 0, defer_factor: bool = False):
+    def __init__(self, desc: B.Desc = None, hbm_budget: int = 0, defer_factor: bool = False, layout=None,
+                 eps=None, k0: float = -1.0, precision=B.MXW_FP64, variant=B.MXW_PREC_ORAS):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required for mxw.Problem")
         self.desc = desc
+        self.layout = layout
         h = C.c_void_p()
-        st = B.lib().mxw_problem_create(C.byref(desc.c), _stream(), hbm_budget, int(defer_factor), C.byref(h))
+        if layout is None:
+            st = B.lib().mxw_problem_create(C.byref(desc.c), _stream(), hbm_budget, int(defer_factor), C.byref(h))
+        else:
+            e = None
+            if eps is not None:
+                e = np.asarray(eps, dtype=np.complex128)
+                self._eps = np.ascontiguousarray(np.stack([e.real, e.imag], axis=1))
+                e = self._eps.ctypes.data
+            st = B.lib().mxw_problem_create_from_layout(layout.h, e, float(k0), int(precision), int(variant),
+                                                        _stream(), hbm_budget, int(defer_factor), C.byref(h))
         self.h = h
         self.create_status = st
         if st != B.MXW_OK and not (st == B.MXW_ESINGULAR and h.value):
             B.check(st)
         self._info = self.info()
+
+    @classmethod
+    def from_layout(cls, layout, eps=None, k0=-1.0, precision=B.MXW_FP64, variant=B.MXW_PREC_ORAS, **kw):
+        """Problem on an existing layout's mesh and partition with a new medium."""
+        return cls(layout=layout, eps=eps, k0=k0, precision=precision, variant=variant, **kw)
+
+    def close(self):
+        """Release the device memory now (instead of at garbage collection)."""
+        if getattr(self, "h", None) is not None and self.h.value:
+            B.lib().mxw_problem_destroy(self.h)
+            self.h = None
 
     @classmethod
     def from_problem(cls, prob, precision=B.MXW_FP64, variant=B.MXW_PREC_ORAS, **kw):
@@ -152,6 +174,14 @@ class Problem:
         allowed = (B.MXW_OK, B.MXW_ENOTCONV, B.MXW_EBREAKDOWN) if allow_notconv else (B.MXW_OK,)
         status = B.check(st, allowed)
         return x, it, rr, status
+
+    def history(self, col: int = 0) -> np.ndarray:
+        """Relative residual estimates of every Arnoldi step of the last solve."""
+        n = C.c_int32()
+        B.check(B.lib().mxw_solve_history(self.h, col, None, 0, C.byref(n)))
+        out = np.empty(n.value, np.float64)
+        B.check(B.lib().mxw_solve_history(self.h, col, out.ctypes.data, n.value, C.byref(n)))
+        return out
 
     def solve(self, sources, **kw):
         b = self.rhs(sources)

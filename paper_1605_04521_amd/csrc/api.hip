@@ -106,8 +106,41 @@ struct DevMem {
 
 using namespace mxw;
 
-struct mxw_layout {
+// Host layout plus its device mirror (geometry, numbering, subdomain maps and
+// the geometric face matrices), shared by every problem built on it.
+struct LayoutShared {
   Layout L;
+  std::mutex mu;
+  bool on_device = false;
+  int device = -1;
+  DevMem mem;
+  double* xyz = nullptr;
+  int* tets = nullptr;
+  int* tet_dofs = nullptr;
+  Term *phi = nullptr, *curl = nullptr, *fphi = nullptr;
+  double* BF = nullptr;
+  int *ft_vert = nullptr, *ft_dofs = nullptr;
+  int64_t* rowptr = nullptr;
+  int* cols = nullptr;
+  int* dof_ent = nullptr;
+  int64_t *ent_tet_ptr = nullptr, *ent_imp_ptr = nullptr;
+  int *ent_tets = nullptr, *ent_imps = nullptr;
+  int *imp_ft = nullptr, *imp_opp = nullptr;
+  double *gx = nullptr, *gw = nullptr;
+  int nq = 0;
+  int64_t *foff = nullptr, *poff = nullptr, *sub_tet_ptr = nullptr, *sub_face_ptr = nullptr;
+  int *nsz = nullptr, *lds = nullptr, *sub_dofs = nullptr, *sub_tets = nullptr, *sub_lmap = nullptr;
+  int *sub_face_ft = nullptr, *sub_face_lmap = nullptr, *order = nullptr;
+  uint8_t* pou = nullptr;
+  int64_t *gall_ptr = nullptr, *gall_pos = nullptr;
+  uint64_t factor_elems = 0;
+  std::vector<int64_t> h_foff;
+  std::vector<int> h_lds, h_order;
+  std::vector<int> h_imp_opp;
+};
+
+struct mxw_layout {
+  std::shared_ptr<LayoutShared> S;
 };
 
 struct KrylovWork {
@@ -119,44 +152,46 @@ struct KrylovWork {
   double *cs = nullptr, *hn = nullptr, *w0 = nullptr, *npart = nullptr, *est = nullptr, *beta = nullptr;
   int *active = nullptr, *jd = nullptr;
   double* host = nullptr;   // pinned: est, hn, w0 for every column
+  std::vector<std::vector<double>> history;   // per column: |g_{j+1}| / ||b|| of every step
 };
 
 struct mxw_problem {
-  Layout L;
+  explicit mxw_problem(std::shared_ptr<LayoutShared> s) : S(std::move(s)), L(S->L) {}
+  std::shared_ptr<LayoutShared> S;
+  const Layout& L;
   int device = 0;
+  int variant = MXW_PREC_ORAS;
+  double k0 = 0.0;
   DevMem mem;
-  // geometry / basis
+  // per-problem (medium dependent) device data
+  double* eps = nullptr;
+  double *imp_beta = nullptr, *imp_eps = nullptr, *sub_face_coef = nullptr;
+  double2* AT = nullptr;
+  double2* vals = nullptr;
+  int *perm = nullptr, *info = nullptr;
+  void* F = nullptr;
+  void* lu_scratch = nullptr;
+  // views of the shared layout mirror
   double* xyz = nullptr;
   int* tets = nullptr;
-  double* eps = nullptr;
   int* tet_dofs = nullptr;
   Term *phi = nullptr, *curl = nullptr, *fphi = nullptr;
-  double2* AT = nullptr;
   double* BF = nullptr;
   int *ft_vert = nullptr, *ft_dofs = nullptr;
-  // global matrix
   int64_t* rowptr = nullptr;
   int* cols = nullptr;
-  double2* vals = nullptr;
   int* dof_ent = nullptr;
   int64_t *ent_tet_ptr = nullptr, *ent_imp_ptr = nullptr;
   int *ent_tets = nullptr, *ent_imps = nullptr;
   int *imp_ft = nullptr, *imp_opp = nullptr;
-  double *imp_beta = nullptr, *imp_eps = nullptr;
   double *gx = nullptr, *gw = nullptr;
   int nq = 0;
-  // subdomains
   int64_t *foff = nullptr, *poff = nullptr, *sub_tet_ptr = nullptr, *sub_face_ptr = nullptr;
-  int *nsz = nullptr, *lds = nullptr, *perm = nullptr, *sub_dofs = nullptr, *sub_tets = nullptr, *sub_lmap = nullptr;
-  int *sub_face_ft = nullptr, *sub_face_lmap = nullptr, *info = nullptr, *order = nullptr;
+  int *nsz = nullptr, *lds = nullptr, *sub_dofs = nullptr, *sub_tets = nullptr, *sub_lmap = nullptr;
+  int *sub_face_ft = nullptr, *sub_face_lmap = nullptr, *order = nullptr;
   uint8_t* pou = nullptr;
-  double* sub_face_coef = nullptr;
   int64_t *gall_ptr = nullptr, *gall_pos = nullptr;
-  void* F = nullptr;
-  void* lu_scratch = nullptr;
   uint64_t factor_elems = 0;
-  std::vector<int64_t> h_foff;
-  std::vector<int> h_lds, h_order;
   bool factored = false;
   bool mixed = false;
   int spmv_group = 16;
@@ -285,7 +320,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   k.W = k.mem.alloc<double2>((size_t)nrhs * n);
   k.X = k.mem.alloc<double2>((size_t)nrhs * n);
   k.Rv = k.mem.alloc<double2>((size_t)nrhs * n);
-  k.YS = P->L.variant == MXW_PREC_OAS ? k.mem.alloc<double2>((size_t)nrhs * P->L.sum_ns) : nullptr;
+  k.YS = P->variant == MXW_PREC_OAS ? k.mem.alloc<double2>((size_t)nrhs * P->L.sum_ns) : nullptr;
   k.h1 = k.mem.alloc<double2>((size_t)nrhs * maxv);
   k.h2 = k.mem.alloc<double2>((size_t)nrhs * maxv);
   k.part = k.mem.alloc<double2>((size_t)nrhs * nblk * maxv);
@@ -303,7 +338,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   k.jd = k.mem.alloc<int>(nrhs);
   if (!k.V || !k.Z || !k.W || !k.X || !k.Rv || !k.h1 || !k.h2 || !k.part || !k.H || !k.sn || !k.g || !k.y ||
       !k.cs || !k.hn || !k.w0 || !k.npart || !k.est || !k.beta || !k.active || !k.jd ||
-      (P->L.variant == MXW_PREC_OAS && !k.YS)) {
+      (P->variant == MXW_PREC_OAS && !k.YS)) {
     k.V = nullptr;
     set_error("Krylov workspace allocation failed");
     return MXW_ENOMEM;
@@ -322,7 +357,7 @@ void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vs
   LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
                    P->order};
   const int64_t n = P->L.ndof;
-  const bool oas = P->L.variant == MXW_PREC_OAS;
+  const bool oas = P->variant == MXW_PREC_OAS;
   if (P->mixed)
     launch_local_solve<float>(st, a, (const float*)P->F, v, vstride, z, zstride, oas ? ys : nullptr, P->L.sum_ns, ncol,
                               active);
@@ -413,7 +448,8 @@ mxw_status mxw_layout_create(const mxw_problem_desc* desc, mxw_layout** out) {
     return MXW_ENOMEM;
   }
   try {
-    TRY(build_layout(desc, l->L));
+    l->S = std::make_shared<LayoutShared>();
+    TRY(build_layout(desc, l->S->L));
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed");
     return MXW_ENOMEM;
@@ -442,7 +478,7 @@ mxw_status mxw_layout_get_info(const mxw_layout* layout, mxw_layout_info* info) 
     set_error("NULL argument");
     return MXW_EINVAL;
   }
-  fill_info(layout->L, info);
+  fill_info(layout->S->L, info);
   return MXW_OK;
 }
 
@@ -451,7 +487,7 @@ mxw_status mxw_export_dofs(const mxw_layout* layout, int8_t* ent_kind, int64_t* 
     set_error("NULL argument");
     return MXW_EINVAL;
   }
-  const Layout& L = layout->L;
+  const Layout& L = layout->S->L;
   std::copy(L.ent_kind.begin(), L.ent_kind.end(), ent_kind);
   std::copy(L.ent_id.begin(), L.ent_id.end(), ent_id);
   std::copy(L.ent_local.begin(), L.ent_local.end(), ent_local);
@@ -463,8 +499,9 @@ mxw_status mxw_export_pattern(const mxw_layout* layout, int64_t* rowptr, int32_t
     set_error("NULL argument");
     return MXW_EINVAL;
   }
-  std::copy(layout->L.rowptr.begin(), layout->L.rowptr.end(), rowptr);
-  std::copy(layout->L.cols.begin(), layout->L.cols.end(), cols);
+  const Layout& L = layout->S->L;
+  std::copy(L.rowptr.begin(), L.rowptr.end(), rowptr);
+  std::copy(L.cols.begin(), L.cols.end(), cols);
   return MXW_OK;
 }
 
@@ -473,7 +510,7 @@ mxw_status mxw_export_subdomain(const mxw_layout* layout, int32_t s, int64_t* n_
     set_error("NULL argument");
     return MXW_EINVAL;
   }
-  const Layout& L = layout->L;
+  const Layout& L = layout->S->L;
   if (s < 0 || s >= L.n_sub) {
     set_error("subdomain id out of range");
     return MXW_EINVAL;
@@ -493,92 +530,65 @@ mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int
     return MXW_EINVAL;
   }
   const int m = opts ? opts->restart : 50;
-  const Layout& L = layout->L;
+  const Layout& L = layout->S->L;
   *bytes = base_bytes(L) + factor_bytes(L, precision) + krylov_bytes(L.ndof, std::max(nrhs, 1), m);
   return MXW_OK;
 }
 
-mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64_t hbm_budget, int32_t defer_factor,
-                              mxw_problem** out) {
-  if (!out) {
-    set_error("out is NULL");
-    return MXW_EINVAL;
-  }
-  *out = nullptr;
-  std::unique_ptr<mxw_problem> P(new (std::nothrow) mxw_problem());
-  if (!P) {
-    set_error("host allocation failed");
-    return MXW_ENOMEM;
-  }
-  try {
-    TRY(build_layout(desc, P->L));
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return MXW_ENOMEM;
-  }
-  Layout& L = P->L;
-  hipStream_t st = (hipStream_t)stream;
-  HIP_CHECK(hipGetDevice(&P->device));
-  P->mixed = L.precision == MXW_MIXED;
-  const uint64_t need = base_bytes(L) + factor_bytes(L, L.precision);
-  if (hbm_budget && need > hbm_budget) {
-    std::ostringstream os;
-    os << "problem needs " << need << " device bytes, budget is " << hbm_budget;
-    set_error(os.str());
-    return MXW_ENOMEM;
-  }
-  if ((uint64_t)L.max_ns * 2 * (P->mixed ? 4 : 8) > 150 * 1024) {
-    std::ostringstream os;
-    os << "largest subdomain has " << L.max_ns << " unknowns; the local solve keeps one local vector in LDS "
-       << "(at most " << 150 * 1024 / (2 * (P->mixed ? 4 : 8)) << " unknowns in this precision)";
-    set_error(os.str());
-    return MXW_EINVAL;
-  }
-  const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
-  DevMem& M = P->mem;
-  TRY(upload(M, P->xyz, L.xyz, st));
-  TRY(upload(M, P->tets, L.tets, st));
-  TRY(upload(M, P->eps, L.eps, st));
-  TRY(upload(M, P->tet_dofs, L.tet_dofs, st));
-  TRY(upload(M, P->phi, L.basis.phi, st));
-  TRY(upload(M, P->curl, L.basis.curl, st));
-  TRY(upload(M, P->fphi, L.basis.fphi, st));
-  TRY(upload(M, P->ft_vert, L.ft_vert, st));
-  TRY(upload(M, P->ft_dofs, L.ft_dofs, st));
-  TRY(upload(M, P->rowptr, L.rowptr, st));
-  TRY(upload(M, P->cols, L.cols, st));
-  TRY(upload(M, P->dof_ent, L.dof_ent, st));
-  TRY(upload(M, P->ent_tet_ptr, L.ent_tet_ptr, st));
-  TRY(upload(M, P->ent_tets, L.ent_tets, st));
-  TRY(upload(M, P->ent_imp_ptr, L.ent_imp_ptr, st));
-  TRY(upload(M, P->ent_imps, L.ent_imps, st));
-  TRY(upload(M, P->imp_ft, L.imp_ft, st));
-  TRY(upload(M, P->imp_beta, L.imp_beta, st));
-  {
-    std::vector<int> opp(L.imp_ft.size());
-    std::vector<double> ie(2 * L.imp_ft.size());
-    for (size_t q = 0; q < L.imp_ft.size(); ++q) {
-      const int32_t f = L.ft_face[L.imp_ft[q]];
-      const int32_t t = L.face_t0[f];
-      const auto& fv = L.faces[f];
-      int o = -1;
-      for (int c = 0; c < 4; ++c) {
-        const int32_t v = L.tets[4 * (int64_t)t + c];
-        if (v != fv[0] && v != fv[1] && v != fv[2]) o = v;
-      }
-      opp[q] = o;
-      ie[2 * q] = L.eps[2 * (int64_t)t];
-      ie[2 * q + 1] = L.eps[2 * (int64_t)t + 1];
+}  // extern "C"
+
+namespace {
+
+// Device mirror of a layout: uploaded once, then shared.
+mxw_status ensure_device_layout(LayoutShared& S, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(S.mu);
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (S.on_device) {
+    if (dev != S.device) {
+      set_error("the layout's device data live on another device");
+      return MXW_EINVAL;
     }
-    TRY(upload(M, P->imp_opp, opp, st));
-    TRY(upload(M, P->imp_eps, ie, st));
-    std::vector<double> gx, gw;
-    P->nq = L.r + 3;
-    gauss_legendre01(P->nq, gx, gw);
-    TRY(upload(M, P->gx, gx, st));
-    TRY(upload(M, P->gw, gw, st));
+    return MXW_OK;
   }
-  // subdomain arrays
+  const Layout& L = S.L;
+  DevMem& M = S.mem;
+  TRY(upload(M, S.xyz, L.xyz, st));
+  TRY(upload(M, S.tets, L.tets, st));
+  TRY(upload(M, S.tet_dofs, L.tet_dofs, st));
+  TRY(upload(M, S.phi, L.basis.phi, st));
+  TRY(upload(M, S.curl, L.basis.curl, st));
+  TRY(upload(M, S.fphi, L.basis.fphi, st));
+  TRY(upload(M, S.ft_vert, L.ft_vert, st));
+  TRY(upload(M, S.ft_dofs, L.ft_dofs, st));
+  TRY(upload(M, S.rowptr, L.rowptr, st));
+  TRY(upload(M, S.cols, L.cols, st));
+  TRY(upload(M, S.dof_ent, L.dof_ent, st));
+  TRY(upload(M, S.ent_tet_ptr, L.ent_tet_ptr, st));
+  TRY(upload(M, S.ent_tets, L.ent_tets, st));
+  TRY(upload(M, S.ent_imp_ptr, L.ent_imp_ptr, st));
+  TRY(upload(M, S.ent_imps, L.ent_imps, st));
+  TRY(upload(M, S.imp_ft, L.imp_ft, st));
+  S.h_imp_opp.resize(L.imp_ft.size());
+  for (size_t q = 0; q < L.imp_ft.size(); ++q) {
+    const int32_t f = L.ft_face[L.imp_ft[q]];
+    const int32_t t = L.imp_tet[q];
+    const auto& fv = L.faces[f];
+    int o = -1;
+    for (int c = 0; c < 4; ++c) {
+      const int32_t v = L.tets[4 * (int64_t)t + c];
+      if (v != fv[0] && v != fv[1] && v != fv[2]) o = v;
+    }
+    S.h_imp_opp[q] = o;
+  }
+  TRY(upload(M, S.imp_opp, S.h_imp_opp, st));
+  {
+    std::vector<double> gx, gw;
+    S.nq = L.r + 3;
+    gauss_legendre01(S.nq, gx, gw);
+    TRY(upload(M, S.gx, gx, st));
+    TRY(upload(M, S.gw, gw, st));
+  }
   {
     std::vector<int64_t> foff(L.n_sub), poff(L.n_sub + 1);
     std::vector<int> nsz(L.n_sub), lds(L.n_sub);
@@ -592,48 +602,157 @@ mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64
       poff[s] = L.sub_dof_ptr[s];
     }
     poff[L.n_sub] = L.sub_dof_ptr[L.n_sub];
-    P->factor_elems = off;
-    P->h_foff = foff;
-    P->h_lds = lds;
+    S.factor_elems = off;
+    S.h_foff = foff;
+    S.h_lds = lds;
     std::vector<int> order(L.n_sub);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nsz[a] > nsz[b]; });
-    P->h_order = order;
-    TRY(upload(M, P->foff, foff, st));
-    TRY(upload(M, P->poff, poff, st));
-    TRY(upload(M, P->nsz, nsz, st));
-    TRY(upload(M, P->lds, lds, st));
-    TRY(upload(M, P->order, order, st));
-    std::vector<int> sd(L.sub_dofs.begin(), L.sub_dofs.end());
-    TRY(upload(M, P->sub_dofs, sd, st));
-    TRY(upload(M, P->pou, L.sub_pou, st));
-    TRY(upload(M, P->sub_tet_ptr, L.sub_tet_ptr, st));
-    TRY(upload(M, P->sub_tets, L.sub_tets, st));
-    TRY(upload(M, P->sub_lmap, L.sub_lmap, st));
-    TRY(upload(M, P->sub_face_ptr, L.sub_face_ptr, st));
-    TRY(upload(M, P->sub_face_ft, L.sub_face_ft, st));
-    TRY(upload(M, P->sub_face_coef, L.sub_face_coef, st));
-    TRY(upload(M, P->sub_face_lmap, L.sub_face_lmap, st));
-    if (L.variant == MXW_PREC_OAS) {
-      // unknown -> positions in every subdomain's local vector, subdomain order
-      std::vector<int64_t> cnt(L.ndof + 1, 0);
-      for (int64_t q = 0; q < (int64_t)L.sub_dofs.size(); ++q) cnt[L.sub_dofs[q] + 1]++;
-      for (int64_t i = 0; i < L.ndof; ++i) cnt[i + 1] += cnt[i];
-      std::vector<int64_t> pos(L.sub_dofs.size()), fill(cnt.begin(), cnt.end() - 1);
-      for (int64_t q = 0; q < (int64_t)L.sub_dofs.size(); ++q) pos[fill[L.sub_dofs[q]]++] = q;
-      TRY(upload(M, P->gall_ptr, cnt, st));
-      TRY(upload(M, P->gall_pos, pos, st));
-    }
+    S.h_order = order;
+    TRY(upload(M, S.foff, foff, st));
+    TRY(upload(M, S.poff, poff, st));
+    TRY(upload(M, S.nsz, nsz, st));
+    TRY(upload(M, S.lds, lds, st));
+    TRY(upload(M, S.order, order, st));
+    TRY(upload(M, S.sub_dofs, L.sub_dofs, st));
+    TRY(upload(M, S.pou, L.sub_pou, st));
+    TRY(upload(M, S.sub_tet_ptr, L.sub_tet_ptr, st));
+    TRY(upload(M, S.sub_tets, L.sub_tets, st));
+    TRY(upload(M, S.sub_lmap, L.sub_lmap, st));
+    TRY(upload(M, S.sub_face_ptr, L.sub_face_ptr, st));
+    TRY(upload(M, S.sub_face_ft, L.sub_face_ft, st));
+    TRY(upload(M, S.sub_face_lmap, L.sub_face_lmap, st));
+    // unknown -> positions in every subdomain's local vector, subdomain order
+    std::vector<int64_t> cnt(L.ndof + 1, 0);
+    for (int64_t q = 0; q < (int64_t)L.sub_dofs.size(); ++q) cnt[L.sub_dofs[q] + 1]++;
+    for (int64_t i = 0; i < L.ndof; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int64_t> pos(L.sub_dofs.size()), fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t q = 0; q < (int64_t)L.sub_dofs.size(); ++q) pos[fill[L.sub_dofs[q]]++] = q;
+    TRY(upload(M, S.gall_ptr, cnt, st));
+    TRY(upload(M, S.gall_pos, pos, st));
   }
+  const int nfloc = L.basis.nfloc;
+  S.BF = M.alloc<double>(L.ft_face.size() * nfloc * nfloc);
+  if (!S.BF) {
+    set_error("device allocation failed (face matrices)");
+    return MXW_ENOMEM;
+  }
+  {
+    ScopedTimer tm(st, "assemble");
+    launch_face(st, (int64_t)L.ft_face.size(), S.xyz, S.ft_vert, S.fphi, nfloc, S.BF);
+  }
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(st));
+  S.device = dev;
+  S.on_device = true;
+  return MXW_OK;
+}
+
+mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* eps_in, double k0, int precision,
+                          int variant, hipStream_t st, uint64_t hbm_budget, int defer_factor, mxw_problem** out) {
+  const Layout& L = S->L;
+  if (precision != MXW_FP64 && precision != MXW_MIXED) {
+    set_error("unknown precision");
+    return MXW_EINVAL;
+  }
+  if (variant != MXW_PREC_ORAS && variant != MXW_PREC_OAS) {
+    set_error("preconditioner variant not available (ORAS and OAS are)");
+    return MXW_EINVAL;
+  }
+  if (!std::isfinite(k0) || k0 < 0) {
+    set_error("k0 must be finite and >= 0");
+    return MXW_EINVAL;
+  }
+  const double* eps = eps_in ? eps_in : L.eps.data();
+  for (int64_t q = 0; q < 2 * L.nt; ++q)
+    if (!std::isfinite(eps[q])) {
+      set_error("non-finite permittivity");
+      return MXW_EINVAL;
+    }
+  const bool mixed = precision == MXW_MIXED;
+  if ((uint64_t)L.max_ns * 2 * (mixed ? 4 : 8) > 150 * 1024) {
+    std::ostringstream os;
+    os << "largest subdomain has " << L.max_ns << " unknowns; the local solve keeps one local vector in LDS "
+       << "(at most " << 150 * 1024 / (2 * (mixed ? 4 : 8)) << " unknowns in this precision)";
+    set_error(os.str());
+    return MXW_EINVAL;
+  }
+  const uint64_t need = base_bytes(L) + factor_bytes(L, precision);
+  if (hbm_budget && need > hbm_budget) {
+    std::ostringstream os;
+    os << "problem needs " << need << " device bytes, budget is " << hbm_budget;
+    set_error(os.str());
+    return MXW_ENOMEM;
+  }
+  TRY(ensure_device_layout(*S, st));
+  std::unique_ptr<mxw_problem> P(new (std::nothrow) mxw_problem(S));
+  if (!P) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  P->device = S->device;
+  P->variant = variant;
+  P->k0 = k0;
+  P->mixed = mixed;
+  // views of the shared mirror
+  P->xyz = S->xyz;
+  P->tets = S->tets;
+  P->tet_dofs = S->tet_dofs;
+  P->phi = S->phi;
+  P->curl = S->curl;
+  P->fphi = S->fphi;
+  P->BF = S->BF;
+  P->ft_vert = S->ft_vert;
+  P->ft_dofs = S->ft_dofs;
+  P->rowptr = S->rowptr;
+  P->cols = S->cols;
+  P->dof_ent = S->dof_ent;
+  P->ent_tet_ptr = S->ent_tet_ptr;
+  P->ent_imp_ptr = S->ent_imp_ptr;
+  P->ent_tets = S->ent_tets;
+  P->ent_imps = S->ent_imps;
+  P->imp_ft = S->imp_ft;
+  P->imp_opp = S->imp_opp;
+  P->gx = S->gx;
+  P->gw = S->gw;
+  P->nq = S->nq;
+  P->foff = S->foff;
+  P->poff = S->poff;
+  P->sub_tet_ptr = S->sub_tet_ptr;
+  P->sub_face_ptr = S->sub_face_ptr;
+  P->nsz = S->nsz;
+  P->lds = S->lds;
+  P->sub_dofs = S->sub_dofs;
+  P->sub_tets = S->sub_tets;
+  P->sub_lmap = S->sub_lmap;
+  P->sub_face_ft = S->sub_face_ft;
+  P->sub_face_lmap = S->sub_face_lmap;
+  P->order = S->order;
+  P->pou = S->pou;
+  P->gall_ptr = S->gall_ptr;
+  P->gall_pos = S->gall_pos;
+  P->factor_elems = S->factor_elems;
+  // medium-dependent data
+  const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
+  DevMem& M = P->mem;
+  std::vector<double> eps_v(eps, eps + 2 * L.nt), beta, coef, ie(2 * L.imp_tet.size());
+  face_coefficients(L, eps, k0, beta, coef);
+  for (size_t q = 0; q < L.imp_tet.size(); ++q) {
+    ie[2 * q] = eps[2 * (int64_t)L.imp_tet[q]];
+    ie[2 * q + 1] = eps[2 * (int64_t)L.imp_tet[q] + 1];
+  }
+  TRY(upload(M, P->eps, eps_v, st));
+  TRY(upload(M, P->imp_beta, beta, st));
+  TRY(upload(M, P->imp_eps, ie, st));
+  TRY(upload(M, P->sub_face_coef, coef, st));
   P->perm = M.alloc<int>(L.sum_ns);
   P->info = M.alloc<int>(L.n_sub);
-  const size_t rsz = P->mixed ? 4 : 8;
+  const size_t rsz = mixed ? 4 : 8;
   P->F = M.alloc<unsigned char>(P->factor_elems * rsz);
   P->lu_scratch = M.alloc<unsigned char>((size_t)L.n_sub * 2 * kLuNB * kLuNB * rsz);
   P->AT = M.alloc<double2>((size_t)L.nt * nloc * nloc);
-  P->BF = M.alloc<double>(L.ft_face.size() * nfloc * nfloc);
   P->vals = M.alloc<double2>(L.cols.size());
-  if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->BF || !P->vals) {
+  if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->vals) {
     set_error("device allocation failed (factors or element data)");
     return MXW_ENOMEM;
   }
@@ -641,11 +760,10 @@ mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64
     const size_t dyn = 2 * (size_t)L.max_ns;
     HIP_CHECK(prepare_local_solve(dyn * 8, dyn * 4));
   }
-  // FP64 element and face matrices, CSR assembly of A
+  // FP64 element matrices and CSR assembly of A
   {
     ScopedTimer tm(st, "assemble");
-    launch_element(st, L.nt, P->xyz, P->tets, P->eps, P->phi, P->curl, nloc, L.basis.ncurl_max, L.k0 * L.k0, P->AT);
-    launch_face(st, (int64_t)L.ft_face.size(), P->xyz, P->ft_vert, P->fphi, nfloc, P->BF);
+    launch_element(st, L.nt, P->xyz, P->tets, P->eps, P->phi, P->curl, nloc, L.basis.ncurl_max, k0 * k0, P->AT);
     AssembleArgs aa{L.ndof, P->rowptr, P->cols, P->dof_ent, P->ent_tet_ptr, P->ent_tets, P->ent_imp_ptr, P->ent_imps,
                     P->tet_dofs, nloc, P->AT, P->imp_ft, P->imp_beta, P->ft_dofs, nfloc, P->BF, P->vals};
     launch_assemble_rows(st, aa);
@@ -658,16 +776,48 @@ mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64
   else
     TRY(build_local_and_factor<double>(P.get(), st, false));
   HIP_CHECK(hipStreamSynchronize(st));
+  mxw_status result = MXW_OK;
   if (!defer_factor) {
-    mxw_status s = factor_impl(P.get(), st);
-    if (s != MXW_OK && s != MXW_ESINGULAR) return s;
-    if (s == MXW_ESINGULAR) {
-      *out = P.release();
-      return s;
-    }
+    result = factor_impl(P.get(), st);
+    if (result != MXW_OK && result != MXW_ESINGULAR) return result;
   }
   *out = P.release();
-  return MXW_OK;
+  return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64_t hbm_budget, int32_t defer_factor,
+                              mxw_problem** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return MXW_EINVAL;
+  }
+  *out = nullptr;
+  std::shared_ptr<LayoutShared> S;
+  try {
+    S = std::make_shared<LayoutShared>();
+    TRY(build_layout(desc, S->L));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  return create_problem(S, nullptr, S->L.k0, desc->precision, desc->prec_variant, (hipStream_t)stream, hbm_budget,
+                        defer_factor, out);
+}
+
+mxw_status mxw_problem_create_from_layout(const mxw_layout* layout, const double* eps, double k0, int32_t precision,
+                                          int32_t prec_variant, void* stream, uint64_t hbm_budget,
+                                          int32_t defer_factor, mxw_problem** out) {
+  if (!out || !layout) {
+    set_error("NULL argument");
+    return MXW_EINVAL;
+  }
+  *out = nullptr;
+  return create_problem(layout->S, eps, k0 < 0 ? layout->S->L.k0 : k0, precision, prec_variant,
+                        (hipStream_t)stream, hbm_budget, defer_factor, out);
 }
 
 void mxw_problem_destroy(mxw_problem* prob) {
@@ -713,11 +863,11 @@ mxw_status mxw_problem_export_local(const mxw_problem* prob, int32_t s, double* 
     return MXW_EINVAL;
   }
   const int64_t n = prob->L.sub_dof_ptr[s + 1] - prob->L.sub_dof_ptr[s];
-  const int64_t ld = prob->h_lds[s];
+  const int64_t ld = prob->S->h_lds[s];
   const size_t rsz = prob->mixed ? 4 : 8;
   std::vector<unsigned char> buf(2 * ld * n * rsz);
   HIP_CHECK(hipDeviceSynchronize());
-  HIP_CHECK(hipMemcpy(buf.data(), (unsigned char*)prob->F + prob->h_foff[s] * rsz, buf.size(), hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemcpy(buf.data(), (unsigned char*)prob->F + prob->S->h_foff[s] * rsz, buf.size(), hipMemcpyDeviceToHost));
   for (int64_t j = 0; j < n; ++j)
     for (int64_t i = 0; i < n; ++i) {
       double re, im;
@@ -791,7 +941,7 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
         HIP_CHECK(hipMallocAsync((void**)&work, sizeof(double2) * std::max<size_t>(1, L.imp_ft.size() * L.basis.nfloc), st));
       }
       PlaneWaveArgs pa{(int)L.imp_ft.size(), n, prob->xyz, prob->ft_vert, prob->imp_ft, prob->imp_opp, prob->imp_beta,
-                       prob->imp_eps, prob->fphi, L.basis.nfloc, L.k0, prob->nq, prob->gx, prob->gw, prob->dof_ent,
+                       prob->imp_eps, prob->fphi, L.basis.nfloc, prob->k0, prob->nq, prob->gx, prob->gw, prob->dof_ent,
                        prob->ent_imp_ptr, prob->ent_imps, prob->ft_dofs};
       launch_rhs_planewave(st, pa, S.pol_re, S.pol_im, S.dir, work, b + (int64_t)c * n);
     } else {
@@ -830,7 +980,7 @@ mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double*
   }
   hipStream_t st = (hipStream_t)stream;
   double2* ys = nullptr;
-  if (prob->L.variant == MXW_PREC_OAS) HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
+  if (prob->variant == MXW_PREC_OAS) HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
   apply_prec_dev(prob, st, (const double2*)v_dev, prob->L.ndof, (double2*)z_dev, prob->L.ndof, nrhs, nullptr, ys);
   HIP_CHECK(hipGetLastError());
   if (ys) HIP_CHECK(hipFreeAsync(ys, st));
@@ -868,6 +1018,7 @@ mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, cons
   double* hbuf = k.host;
 
   std::vector<double> bnorm(nrhs), beta(nrhs), relres(nrhs, 1.0);
+  k.history.assign(nrhs, std::vector<double>());
   std::vector<int> iters(nrhs, 0), conv(nrhs, 0), act(nrhs, 0), jd(nrhs, 0);
   launch_norm(st, n, B, n, k.npart, k.beta, nrhs, nullptr);
   HIP_CHECK(hipMemcpyAsync(hbuf, k.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
@@ -937,6 +1088,7 @@ mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, cons
         iters[c]++;
         jd[c] = j + 1;
         const double est = hbuf[c], hn = hbuf[nrhs + c], w0 = hbuf[2 * nrhs + c];
+        k.history[c].push_back(est / bnorm[c]);
         const bool brk = !(hn > 1e-14 * w0);
         if (brk) breakdown_any = true;
         if (est <= opts->tol * bnorm[c] || brk || iters[c] >= opts->max_iters || !std::isfinite(est)) {
@@ -1007,6 +1159,19 @@ mxw_status mxw_solve(mxw_problem* P, int32_t nrhs, const mxw_source* src, const 
   hipFree(b);
   if (!E_out_is_device) hipFree(x);
   return s;
+}
+
+mxw_status mxw_solve_history(const mxw_problem* P, int32_t col, double* out, int32_t max_len, int32_t* len) {
+  TRY(check_problem(P));
+  if (!len || col < 0 || col >= (int32_t)P->kw.history.size()) {
+    set_error("invalid argument (no solve recorded for this column)");
+    return MXW_EINVAL;
+  }
+  const auto& h = P->kw.history[col];
+  *len = (int32_t)h.size();
+  if (out)
+    for (int32_t q = 0; q < std::min<int32_t>(max_len, (int32_t)h.size()); ++q) out[q] = h[q];
+  return MXW_OK;
 }
 
 mxw_status mxw_set_timing(int32_t enabled) {

@@ -287,8 +287,7 @@ mxw_status build_layout(const mxw_problem_desc* d, Layout& L) {
     if (L.face_kind[f] == MXW_BC_IMPEDANCE) {
       int32_t s = slot_of((int32_t)f);
       L.imp_ft.push_back(s);
-      int32_t t = L.face_t0[f];
-      L.imp_beta.push_back(L.k0 * std::sqrt(std::max(0.0, L.eps[2 * t])));
+      L.imp_tet.push_back(L.face_t0[f]);
     }
 
   L.owner.assign(nd, INT32_MAX);
@@ -360,18 +359,16 @@ mxw_status build_layout(const mxw_problem_desc* d, Layout& L) {
         for (int f = 0; f < 4; ++f) {
           int32_t fid = L.tet_faces[4 * (int64_t)t + f];
           int32_t u = L.face_t0[fid] == t ? L.face_t1[fid] : L.face_t0[fid];
-          double coef;
           if (pass == 0) {
             if (L.face_kind[fid] != MXW_BC_IMPEDANCE) continue;
-            coef = L.k0 * std::sqrt(std::max(0.0, L.eps[2 * (int64_t)t]));
           } else {
             if (u < 0 || mark[u] == s) continue;
-            coef = L.k0 * std::sqrt(std::max(0.0, L.eps[2 * (int64_t)t]));
             L.n_iface++;
           }
           int32_t slot = slot_of(fid);
           L.sub_face_ft.push_back(slot);
-          L.sub_face_coef.push_back(coef);
+          L.sub_face_tet.push_back(t);
+          L.sub_face_iface.push_back((uint8_t)pass);
           // face-local unknowns: edges (a,b), (a,c), (b,c), then the face's own
           const auto& v = L.faces[fid];
           std::array<int32_t, 2> es[3] = {{v[0], v[1]}, {v[0], v[2]}, {v[1], v[2]}};
@@ -433,6 +430,15 @@ mxw_status build_layout(const mxw_problem_desc* d, Layout& L) {
     }
   }
   return MXW_OK;
+}
+
+void face_coefficients(const Layout& L, const double* eps, double k0, std::vector<double>& imp_beta,
+                       std::vector<double>& sub_face_coef) {
+  auto wavenumber = [&](int64_t t) { return k0 * std::sqrt(std::max(0.0, eps[2 * t])); };
+  imp_beta.resize(L.imp_tet.size());
+  for (size_t q = 0; q < L.imp_tet.size(); ++q) imp_beta[q] = wavenumber(L.imp_tet[q]);
+  sub_face_coef.resize(L.sub_face_tet.size());
+  for (size_t q = 0; q < L.sub_face_tet.size(); ++q) sub_face_coef[q] = wavenumber(L.sub_face_tet[q]);
 }
 
 }  // namespace mxw

@@ -97,7 +97,7 @@ struct Layout {
   std::vector<int32_t> ft_dofs;          // [nft][nfloc] global unknowns (-1 eliminated)
   std::vector<int32_t> face_slot;        // face id -> table index or -1
   std::vector<int32_t> imp_ft;           // table indices of impedance boundary faces
-  std::vector<double> imp_beta;          // beta of each impedance face
+  std::vector<int32_t> imp_tet;          // the element adjacent to each impedance face
 
   // ---- subdomains
   std::vector<int64_t> sub_dof_ptr;      // [n_sub+1]
@@ -108,7 +108,8 @@ struct Layout {
   std::vector<int32_t> sub_lmap;         // [sum |Omega_s|][nloc] local positions
   std::vector<int64_t> sub_face_ptr;     // [n_sub+1]
   std::vector<int32_t> sub_face_ft;      // face table index
-  std::vector<double> sub_face_coef;     // beta (boundary) or w~ (interface)
+  std::vector<int32_t> sub_face_tet;     // element of Omega_s owning the face
+  std::vector<uint8_t> sub_face_iface;   // 0 original impedance face, 1 interface face
   std::vector<int32_t> sub_face_lmap;    // [.][nfloc]
   std::vector<int32_t> owner;            // [ndof] owning subdomain
   std::vector<int64_t> owner_pos;        // [ndof] position in the concatenated local vectors
@@ -120,5 +121,11 @@ struct Layout {
 };
 
 mxw_status build_layout(const mxw_problem_desc* d, Layout& L);
+
+// beta of each impedance face and the coefficient of each subdomain face
+// (beta on original impedance faces, w~ on interface faces; both k0 sqrt(Re eps)
+// of the owning element) for a permittivity field eps[nt][2]
+void face_coefficients(const Layout& L, const double* eps, double k0, std::vector<double>& imp_beta,
+                       std::vector<double>& sub_face_coef);
 
 }  // namespace mxw
