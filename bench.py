@@ -1,11 +1,12 @@
 """Benchmark: forward Maxwell solves per second on one MI355X.
 
 Workload (default): the synthetic imaging chamber -- cylinder R = 0.15 m,
-H = 0.28 m, 34^3 Kuhn grid mapped to the cylinder, degree-2 edge elements
-(1,470,500 unknowns after removing the metallic wall and bottom), background
-eps = 44+20i with a seeded head (40+15i) and a +-20 % inclusion, 1 GHz,
-RCB core partition, 2 face layers of overlap, FP64 throughout, one z-polarised
-dipole on the 0.14 m ring.  A step is one complete forward solve: FP64 element
+H = 0.28 m meshed as a 5-block O-grid (22 x 11 radial x 27 layers of cells,
+Kuhn-split), degree-2 edge elements (1,477,926 unknowns after removing the
+metallic wall and bottom), background eps = 44+20i with a seeded head
+(40+15i) and a +-20 % inclusion, 1 GHz, 3,465 block-aligned core subdomains
+(2 x 2 x 3 cells each), 2 face layers of overlap (n_s <= 2,010), FP64
+throughout, one z-polarised dipole on the 0.14 m ring.  A step is one complete forward solve: FP64 element
 matrices with this step's medium, CSR assembly of A, dense local matrices
 A_s, batched LU of every A_s, right-hand side, and ORAS-preconditioned FGMRES
 to a true relative residual of 1e-8.  The per-mesh host setup (entity
@@ -129,9 +130,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chamber", choices=["chamber", "cube"])
-    ap.add_argument("--n", type=int, default=34)
+    ap.add_argument("--n", type=int, default=22)
+    ap.add_argument("--nz", type=int, default=27)
     ap.add_argument("--degree", type=int, default=2)
-    ap.add_argument("--nsub", type=int, default=6000)
+    ap.add_argument("--nsub", default="2x2x3",
+                    help="RCB subdomain count, or AxBxC cells per block-aligned core subdomain")
     ap.add_argument("--overlap", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--nrhs", type=int, default=1)
@@ -157,10 +160,13 @@ def main():
 
     t0 = time.perf_counter()
     if args.workload == "chamber":
-        prob = gen.chamber_problem(n=args.n, degree=args.degree, n_sub=args.nsub, overlap=args.overlap,
+        nsub = tuple(int(q) for q in args.nsub.split("x")) if "x" in args.nsub else int(args.nsub)
+        prob = gen.chamber_problem(n=args.n, nz=args.nz, degree=args.degree, n_sub=nsub, overlap=args.overlap,
                                    seed=args.seed, n_sources=args.nrhs)
-        wl = (f"imaging chamber R=0.15 m H=0.28 m, Kuhn {args.n}^3 mapped, r={args.degree}, "
-              f"{args.nsub} RCB subdomains, {args.overlap} face layers, {args.nrhs} dipole(s)")
+        kind = f"{args.nsub}-cell block-aligned" if "x" in args.nsub else "RCB"
+        wl = (f"imaging chamber cylinder R=0.15 m H=0.28 m, O-grid {args.n}x{args.n // 2}x{args.nz}, "
+              f"r={args.degree}, {prob.n_sub} {kind} subdomains, {args.overlap} face layers, "
+              f"{args.nrhs} dipole(s), eps 44+20i / head 40+15i / inclusion")
     else:
         prob = gen.cube_planewave_problem(n=args.n, degree=args.degree, seed=args.seed, n_sources=args.nrhs)
         wl = f"unit cube {args.n}^3 Kuhn, r={args.degree}, plane wave, 2x2x2 boxes"

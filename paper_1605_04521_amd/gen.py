@@ -132,7 +132,7 @@ def unit_cube(n: int, bc: int = BC_IMPEDANCE) -> Mesh:
                 grid_n=n, cube_of_tet=cube.astype(np.int32))
 
 
-def chamber_cylinder(n: int, radius: float = 0.15, height: float = 0.28) -> Mesh:
+def chamber_cylinder(n: int, radius: float = 0.15, height: float = 0.28, shape: str = "cylinder") -> Mesh:
     """Cylindrical chamber: Kuhn grid on [-1,1]^2 x [0,1] mapped to a cylinder.
 
     (u,v) -> R (u sqrt(1 - v^2/2), v sqrt(1 - u^2/2)), w -> H w; straight-sided
@@ -146,8 +146,14 @@ def chamber_cylinder(n: int, radius: float = 0.15, height: float = 0.28) -> Mesh
     u = -1.0 + 2.0 * ii.ravel() / n
     v = -1.0 + 2.0 * jj.ravel() / n
     w = kk.ravel() / n
-    x = radius * u * np.sqrt(1.0 - 0.5 * v * v)
-    y = radius * v * np.sqrt(1.0 - 0.5 * u * u)
+    if shape == "cylinder":
+        x = radius * u * np.sqrt(1.0 - 0.5 * v * v)
+        y = radius * v * np.sqrt(1.0 - 0.5 * u * u)
+    elif shape == "box":          # square cross-section [-R,R]^2 (no mapping)
+        x = radius * u
+        y = radius * v
+    else:
+        raise ValueError("shape must be 'cylinder' or 'box'")
     xyz = np.stack([x, y, height * w], axis=1)
 
     def kind(axis, side):
@@ -158,6 +164,126 @@ def chamber_cylinder(n: int, radius: float = 0.15, height: float = 0.28) -> Mesh
     bf, bk = _grid_boundary_faces(n, tets, kind)
     return Mesh(xyz=xyz, tets=tets.astype(np.int32), bfaces=bf, bface_kind=bk,
                 grid_n=n, cube_of_tet=cube.astype(np.int32))
+
+
+def _kuhn_block(vid: np.ndarray) -> np.ndarray:
+    """Kuhn split of a structured block; vid[a,b,c] = global vertex id."""
+    na, nb, nc = (d - 1 for d in vid.shape)
+    A, Bb, Cc = np.meshgrid(np.arange(na), np.arange(nb), np.arange(nc), indexing="ij")
+    A, Bb, Cc = A.ravel(), Bb.ravel(), Cc.ravel()
+    out = np.empty((len(A), 6, 4), dtype=np.int64)
+    for q, (x, y, _) in enumerate(_PERMS):
+        p0 = np.stack([A, Bb, Cc], axis=1)
+        p1 = p0 + _UNIT[x]
+        p2 = p1 + _UNIT[y]
+        p3 = p0 + 1
+        for c, p in enumerate((p0, p1, p2, p3)):
+            out[:, q, c] = vid[p[:, 0], p[:, 1], p[:, 2]]
+    return out.reshape(-1, 4)
+
+
+def _block_faces(vid: np.ndarray, tets: np.ndarray, axis: int, side: int) -> np.ndarray:
+    """Faces of the block's Kuhn tets lying on its face axis=0 (side 0) or axis=max (side 1)."""
+    val = 0 if side == 0 else vid.shape[axis] - 1
+    on = np.zeros(vid.max() + 1, dtype=bool)
+    sl = [slice(None)] * 3
+    sl[axis] = val
+    on[vid[tuple(sl)].ravel()] = True
+    out = []
+    for drop in range(4):
+        keep = [c for c in range(4) if c != drop]
+        fv = tets[:, keep]
+        sel = np.all(on[fv], axis=1)
+        out.append(np.sort(fv[sel], axis=1))
+    return np.concatenate(out)
+
+
+def chamber_ogrid(nc: int, nr: int, nz: int, radius: float = 0.15, height: float = 0.28,
+                  inner: float = 0.5) -> Mesh:
+    """Cylindrical chamber as a 5-block O-grid, each block Kuhn-split.
+
+    Centre block: the square |x|,|y| <= inner*R with nc x nc cells.  Four outer
+    blocks join the square's sides to the circle of radius R: nr radial x nc
+    tangential cells, points blended linearly from the square side to the arc.
+    nz layers in height.  Local axes are oriented so that every face shared by
+    two blocks gets the same diagonal from both sides (a conforming mesh).
+    Lateral wall and bottom are metallic (PEC), the top is an impedance face.
+    No grid corner lies on the circle, so no element degenerates there.
+    """
+    a = inner * radius
+    zc = height * np.arange(nz + 1) / nz
+    tt = -1.0 + 2.0 * np.arange(nc + 1) / nc
+    ss = np.arange(nr + 1) / nr
+    pts, blocks = [], []
+
+    def add(X, Y):
+        """X, Y: [n0+1, n1+1] planar coordinates; returns local vertex ids [n0+1,n1+1,nz+1]."""
+        base = sum(len(p) for p in pts)
+        n0, n1 = X.shape
+        P = np.empty((n0, n1, nz + 1, 3))
+        P[..., 0] = X[:, :, None]
+        P[..., 1] = Y[:, :, None]
+        P[..., 2] = zc[None, None, :]
+        pts.append(P.reshape(-1, 3))
+        return base + np.arange(n0 * n1 * (nz + 1)).reshape(n0, n1, nz + 1)
+
+    # centre: axes (x, y, z)
+    U, V = np.meshgrid(tt, tt, indexing="ij")
+    blocks.append(("centre", add(a * U, a * V)))
+    S, T = np.meshgrid(ss, tt, indexing="ij")           # [radial, tangential]
+    th = T * np.pi / 4
+    specs = {  # inner point (on the square) and outer point (on the circle)
+        "right": ((a + 0 * T, a * T), (radius * np.cos(th), radius * np.sin(th))),
+        "top": ((a * T, a + 0 * T), (radius * np.sin(th), radius * np.cos(th))),
+        "left": ((-a + 0 * T, a * T), (-radius * np.cos(th), radius * np.sin(th))),
+        "bottom": ((a * T, -a + 0 * T), (radius * np.sin(th), -radius * np.cos(th))),
+    }
+    for name, ((xi, yi), (xo, yo)) in specs.items():
+        blocks.append((name, add((1 - S) * xi + S * xo, (1 - S) * yi + S * yo)))
+    xyz_all = np.concatenate(pts)
+    key = np.round(xyz_all / (radius * 1e-9)).astype(np.int64)
+    uniq, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    inv = inv.ravel()
+    # renumber merged vertices in order of first appearance
+    order = np.argsort(first)
+    rank = np.empty_like(order)
+    rank[order] = np.arange(len(order))
+    gid = rank[inv]
+    xyz = xyz_all[first[order]]
+    tets, faces, kinds, cells = [], [], [], []
+    for bi, (name, vid) in enumerate(blocks):
+        g = gid[vid]
+        tb = _kuhn_block(g)
+        tets.append(tb)
+        na, nb, ncz = (d - 1 for d in vid.shape)
+        A, Bb, Cc = np.meshgrid(np.arange(na), np.arange(nb), np.arange(ncz), indexing="ij")
+        cl = np.stack([np.full(A.size, bi), A.ravel(), Bb.ravel(), Cc.ravel()], axis=1)
+        cells.append(np.repeat(cl, 6, axis=0))
+        bot = _block_faces(g, tb, 2, 0)
+        top = _block_faces(g, tb, 2, 1)
+        faces += [bot, top]
+        kinds += [np.full(len(bot), BC_PEC, np.int8), np.full(len(top), BC_IMPEDANCE, np.int8)]
+        if name != "centre":
+            wall = _block_faces(g, tb, 0, 1)
+            faces.append(wall)
+            kinds.append(np.full(len(wall), BC_PEC, np.int8))
+    tets = np.concatenate(tets)
+    faces = np.concatenate(faces)
+    kinds = np.concatenate(kinds)
+    o = np.lexsort((faces[:, 2], faces[:, 1], faces[:, 0]))
+    return Mesh(xyz=xyz, tets=tets.astype(np.int32), bfaces=faces[o].astype(np.int32),
+                bface_kind=kinds[o], grid_n=0, cube_of_tet=np.concatenate(cells).astype(np.int32))
+
+
+def ogrid_block_partition(mesh: Mesh, ba: int, bb: int, bc: int) -> tuple[np.ndarray, int]:
+    """Core subdomains of an O-grid mesh: boxes of ba x bb x bc cells in each
+    block's own (radial or x, tangential or y, z) index space."""
+    cl = mesh.cube_of_tet
+    blk = cl[:, 0]
+    key = np.stack([blk, cl[:, 1] // ba, cl[:, 2] // bb, cl[:, 3] // bc], axis=1)
+    _, part = np.unique(key, axis=0, return_inverse=True)
+    part = part.ravel().astype(np.int32)
+    return part, int(part.max()) + 1
 
 
 def centroids(mesh: Mesh) -> np.ndarray:
@@ -289,19 +415,36 @@ def cube_planewave_problem(n: int = 8, degree: int = 1, box: int = 4, overlap: i
                    name=f"cube n={n} r={degree} box={box} ov={overlap}")
 
 
-def chamber_problem(n: int = 34, degree: int = 2, n_sub: int = 1500, overlap: int = 2,
-                    seed: int = 0, n_sources: int = 1, ring_z: float = 0.196) -> Problem:
+def chamber_problem(n: int = 22, degree: int = 2, n_sub=(2, 2, 3), overlap: int = 2,
+                    seed: int = 0, n_sources: int = 1, ring_z: float = 0.196, shape: str = "cylinder",
+                    nr: int = None, nz: int = None) -> Problem:
     """Synthetic imaging chamber (cylinder R=0.15 m, H=0.28 m) at 1 GHz.
 
-    Background eps = 44+20i, seeded head ellipsoid eps = 40+15i and a
-    +-20 % spherical inclusion; RCB core partition into n_sub parts;
-    z-polarised dipoles on the ring of radius 0.14 m.
+    shape "cylinder": 5-block O-grid with n cells along the centre square's
+    side, nr radial cells (default n//2) and nz layers (default n);
+    the default 22/11/27 gives 1,477,926 degree-2 unknowns.  "mapped" and
+    "box": single-block n^3 Kuhn grids (square mapped to the disc, or a
+    square cross-section).  Background eps = 44+20i, seeded head ellipsoid
+    eps = 40+15i and a +-20 % spherical inclusion.  n_sub: an int gives an
+    RCB core partition into that many parts; a tuple (a, b, c) gives O-grid
+    block-aligned cores of a x b x c cells.  z-polarised dipoles on the ring
+    of radius 0.14 m.
     """
-    mesh = chamber_cylinder(n)
+    if shape == "cylinder":
+        nr = nr if nr is not None else max(1, n // 2)
+        nz = nz if nz is not None else n
+        mesh = chamber_ogrid(n, nr, nz)
+        tag = f"ogrid {n}x{nr}x{nz}"
+    else:
+        mesh = chamber_cylinder(n, shape=shape)
+        tag = f"{shape} {n}^3"
     eps, _ = chamber_eps(mesh, seed)
-    part = rcb_partition(centroids(mesh), n_sub)
+    if isinstance(n_sub, tuple):       # (ba, bb, bc) block-aligned boxes of an O-grid
+        part, n_sub = ogrid_block_partition(mesh, *n_sub)
+    else:
+        part = rcb_partition(centroids(mesh), n_sub)
     srcs = ring_dipoles(32, 0.14, ring_z)[:n_sources] if n_sources <= 32 else \
         [s for z in (0.028, 0.084, 0.140, 0.196, 0.252) for s in ring_dipoles(32, 0.14, z)][:n_sources]
     return Problem(mesh=mesh, eps=eps, part=part, n_sub=n_sub, overlap=overlap,
                    k0=K0_1GHZ, degree=degree, sources=srcs,
-                   name=f"chamber n={n} r={degree} nsub={n_sub} ov={overlap}")
+                   name=f"chamber {tag} r={degree} nsub={n_sub} ov={overlap}")
