@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -178,11 +179,19 @@ def main():
     footprint = lay.footprint(precision, args.nrhs)
     log(f"[bench] device footprint {footprint/1e9:.1f} GB")
 
+    phases = []
+
     def one_step():
+        t0 = time.perf_counter()
         P = Problem.from_layout(lay, eps=prob.eps, k0=prob.k0, precision=precision)
+        t1 = time.perf_counter()
         x, it, rr, st = P.solve(prob.sources[:args.nrhs])
         torch.cuda.synchronize()
+        t2 = time.perf_counter()
         P.close()
+        t3 = time.perf_counter()
+        phases.append((t1 - t0, t2 - t1, t3 - t2))
+        log(f"[bench]   create {t1-t0:.2f}s solve {t2-t1:.2f}s release {t3-t2:.2f}s")
         return it, rr
 
     # first call also builds the layout's device copy (per-mesh, untimed)
@@ -192,7 +201,7 @@ def main():
         log(f"[bench] warmup {w}: iters={it.tolist()} relres={rr.tolist()} {time.perf_counter()-t0:.2f}s")
         t0 = time.perf_counter()
 
-    timing(True)
+    timing(not args.no_kernel_timing)
     reset_timing()
     torch.cuda.synchronize()
     lat = []
@@ -253,6 +262,9 @@ def main():
                    "iterations": iters, "restart": 50, "tol": 1e-8},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "mesh_setup_s": t_mesh,
+        "phase_s": {"create": float(np.median([p[0] for p in phases[-args.steps:]])),
+                    "solve": float(np.median([p[1] for p in phases[-args.steps:]])),
+                    "release": float(np.median([p[2] for p in phases[-args.steps:]]))},
         "roofline": roof,
         "kernels": kern,
     }

@@ -32,16 +32,34 @@ struct TimingRec {
 static std::mutex g_tmu;
 static bool g_timing = false;
 static std::vector<TimingRec> g_pending;
+static std::vector<hipEvent_t> g_event_pool;   // events reused across launches
 static std::map<std::string, std::pair<double, int64_t>> g_totals;
 
+static hipEvent_t pooled_event() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Range timer: events recorded on the stream around a group of launches.
 struct ScopedTimer {
   hipStream_t st;
   const char* name;
   hipEvent_t a = nullptr, b = nullptr;
   ScopedTimer(hipStream_t s, const char* n) : st(s), name(n) {
     if (!g_timing) return;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
+    a = pooled_event();
+    b = pooled_event();
+    if (!a || !b) {
+      a = b = nullptr;
+      return;
+    }
     hipEventRecord(a, st);
   }
   ~ScopedTimer() {
@@ -49,6 +67,49 @@ struct ScopedTimer {
     hipEventRecord(b, st);
     std::lock_guard<std::mutex> lk(g_tmu);
     g_pending.push_back({name, a, b});
+  }
+};
+
+// Kernel timer: the next launch in scope carries the start/stop events in its
+// own dispatch (hipExtLaunchKernelGGL), so timing adds no packets to the stream.
+struct KernelEvents {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool used = false;
+};
+static thread_local KernelEvents* g_kernel_events = nullptr;
+
+bool take_timer_events(hipEvent_t* a, hipEvent_t* b) {
+  KernelEvents* k = g_kernel_events;
+  if (!k || k->used || !k->a) return false;
+  k->used = true;
+  *a = k->a;
+  *b = k->b;
+  return true;
+}
+
+struct ScopedKernelTimer {
+  const char* name;
+  KernelEvents ev;
+  explicit ScopedKernelTimer(const char* n) : name(n) {
+    if (!g_timing) return;
+    ev.a = pooled_event();
+    ev.b = pooled_event();
+    if (!ev.a || !ev.b) {
+      ev.a = ev.b = nullptr;
+      return;
+    }
+    g_kernel_events = &ev;
+  }
+  ~ScopedKernelTimer() {
+    if (!ev.a) return;
+    g_kernel_events = nullptr;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (ev.used) {
+      g_pending.push_back({name, ev.a, ev.b});
+    } else {
+      g_event_pool.push_back(ev.a);
+      g_event_pool.push_back(ev.b);
+    }
   }
 };
 
@@ -61,8 +122,8 @@ static void flush_timing() {
     auto& t = g_totals[r.name];
     t.first += ms;
     t.second += 1;
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    g_event_pool.push_back(r.a);
+    g_event_pool.push_back(r.b);
   }
   g_pending.clear();
 }
@@ -353,7 +414,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
 // z = M^{-1} v for ncol columns (device, stride ndof)
 void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vstride, double2* z, int64_t zstride,
                     int ncol, const int* active, double2* ys) {
-  ScopedTimer tm(st, "local_solve");
+  ScopedKernelTimer tm("local_solve");
   LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
                    P->order};
   const int64_t n = P->L.ndof;
@@ -369,7 +430,7 @@ void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vs
 
 void spmv_dev(mxw_problem* P, hipStream_t st, const double2* x, double2* y, const double2* b, int ncol,
               const int* active) {
-  ScopedTimer tm(st, "spmv");
+  ScopedKernelTimer tm("spmv");
   const int64_t n = P->L.ndof;
   launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, x, n, y, n, b, n, ncol, active);
 }
@@ -394,7 +455,7 @@ mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor) {
   }
   HIP_CHECK(hipGetLastError());
   if (factor) {
-    ScopedTimer tm(st, "lu");
+    ScopedKernelTimer tm("lu");
     launch_lu<R>(st, L.n_sub, (R*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (R*)P->lu_scratch, P->info,
                  P->order);
   }
@@ -407,11 +468,11 @@ mxw_status factor_impl(mxw_problem* P, hipStream_t st) {
   if (P->mixed) {
     const int NB = kLuNB;
     (void)NB;
-    ScopedTimer tm(st, "lu");
+    ScopedKernelTimer tm("lu");
     launch_lu<float>(st, P->L.n_sub, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (float*)P->lu_scratch,
                      P->info, P->order);
   } else {
-    ScopedTimer tm(st, "lu");
+    ScopedKernelTimer tm("lu");
     launch_lu<double>(st, P->L.n_sub, (double*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
                       (double*)P->lu_scratch, P->info, P->order);
   }
@@ -1059,11 +1120,10 @@ mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, cons
       // z_j = M^{-1} v_j (columns at stride vcol / zcol)
       apply_prec_dev(P, st, Vj, vcol, Zj, zcol, nrhs, k.active, k.YS);
       {
-        ScopedTimer tm(st, "spmv");
+        ScopedKernelTimer tm("spmv");
         launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, zcol, k.W, n, nullptr, 0, nrhs, k.active);
       }
       {
-        ScopedTimer tm(st, "cgs");
         launch_norm(st, n, k.W, n, k.npart, k.w0, nrhs, k.active);
         launch_dots(st, n, j + 1, k.V, vcol, k.W, n, k.part, maxv, nrhs, k.active);
         launch_reduce_dots(st, n, j + 1, k.part, k.h1, maxv, 0, nrhs, k.active);

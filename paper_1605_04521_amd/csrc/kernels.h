@@ -1,6 +1,7 @@
 // Kernel launchers (host-callable) of the mxw library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -10,6 +11,19 @@
 namespace mxw {
 
 constexpr int kLuNB = 32;   // LU panel width = block size of the triangular sweeps
+
+// Start/stop events for the next timed launch, if kernel timing is on.
+bool take_timer_events(hipEvent_t* a, hipEvent_t* b);
+
+// Launch through hipExtLaunchKernelGGL when timing events are pending.
+template <typename F, typename... Args>
+inline void timed_launch(F kernel, dim3 grid, dim3 block, unsigned shmem, hipStream_t st, Args... args) {
+  hipEvent_t a, b;
+  if (take_timer_events(&a, &b))
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, a, b, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+}
 
 void launch_element(hipStream_t st, int64_t nt, const double* xyz, const int* tets, const double* eps,
                     const Term* phi, const Term* curl, int nloc, int ncurl, double k0sq, double2* AT);

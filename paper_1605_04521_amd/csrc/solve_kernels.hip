@@ -57,14 +57,19 @@ __global__ void __launch_bounds__(256) k_local_solve(const R* __restrict__ F, co
       const R* cr = Ar + b0 + r;
       const R* ci = Ai + b0 + r;
       int c = cg;
-      for (; c + CG < b0; c += 2 * CG) {
+      for (; c + 3 * CG < b0; c += 4 * CG) {
         const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
         const R l1r = cr[(int64_t)(c + CG) * ld], l1i = ci[(int64_t)(c + CG) * ld];
-        const R x0r = xr[c], x0i = xi[c], x1r = xr[c + CG], x1i = xi[c + CG];
-        s0r += l0r * x0r - l0i * x0i;
-        s0i += l0r * x0i + l0i * x0r;
-        s1r += l1r * x1r - l1i * x1i;
-        s1i += l1r * x1i + l1i * x1r;
+        const R l2r = cr[(int64_t)(c + 2 * CG) * ld], l2i = ci[(int64_t)(c + 2 * CG) * ld];
+        const R l3r = cr[(int64_t)(c + 3 * CG) * ld], l3i = ci[(int64_t)(c + 3 * CG) * ld];
+        s0r += l0r * xr[c] - l0i * xi[c];
+        s0i += l0r * xi[c] + l0i * xr[c];
+        s1r += l1r * xr[c + CG] - l1i * xi[c + CG];
+        s1i += l1r * xi[c + CG] + l1i * xr[c + CG];
+        s0r += l2r * xr[c + 2 * CG] - l2i * xi[c + 2 * CG];
+        s0i += l2r * xi[c + 2 * CG] + l2i * xr[c + 2 * CG];
+        s1r += l3r * xr[c + 3 * CG] - l3i * xi[c + 3 * CG];
+        s1i += l3r * xi[c + 3 * CG] + l3i * xr[c + 3 * CG];
       }
       for (; c < b0; c += CG) {
         const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
@@ -117,14 +122,19 @@ __global__ void __launch_bounds__(256) k_local_solve(const R* __restrict__ F, co
       const R* cr = Ar + b0 + r;
       const R* ci = Ai + b0 + r;
       int c = b0 + bn + cg;
-      for (; c + CG < n; c += 2 * CG) {
+      for (; c + 3 * CG < n; c += 4 * CG) {
         const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
         const R l1r = cr[(int64_t)(c + CG) * ld], l1i = ci[(int64_t)(c + CG) * ld];
-        const R x0r = xr[c], x0i = xi[c], x1r = xr[c + CG], x1i = xi[c + CG];
-        s0r += l0r * x0r - l0i * x0i;
-        s0i += l0r * x0i + l0i * x0r;
-        s1r += l1r * x1r - l1i * x1i;
-        s1i += l1r * x1i + l1i * x1r;
+        const R l2r = cr[(int64_t)(c + 2 * CG) * ld], l2i = ci[(int64_t)(c + 2 * CG) * ld];
+        const R l3r = cr[(int64_t)(c + 3 * CG) * ld], l3i = ci[(int64_t)(c + 3 * CG) * ld];
+        s0r += l0r * xr[c] - l0i * xi[c];
+        s0i += l0r * xi[c] + l0i * xr[c];
+        s1r += l1r * xr[c + CG] - l1i * xi[c + CG];
+        s1i += l1r * xi[c + CG] + l1i * xr[c + CG];
+        s0r += l2r * xr[c + 2 * CG] - l2i * xi[c + 2 * CG];
+        s0i += l2r * xi[c + 2 * CG] + l2i * xr[c + 2 * CG];
+        s1r += l3r * xr[c + 3 * CG] - l3i * xi[c + 3 * CG];
+        s1i += l3r * xi[c + 3 * CG] + l3i * xr[c + 3 * CG];
       }
       for (; c < n; c += CG) {
         const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
@@ -284,18 +294,26 @@ __global__ void __launch_bounds__(kRedThreads) k_dots(int64_t ndof, int nvec, co
   }
 }
 
-// h[col][i] (+)= sum_blk part[col][blk][i]   (fixed order)
-__global__ void k_reduce_dots(int nvec, int nblk, int maxv, const double2* __restrict__ part, double2* __restrict__ h,
-                              int accumulate, const int* __restrict__ active) {
-  const int col = blockIdx.y;
+// h[col][i] (+)= sum_blk part[col][blk][i]; one block per (i, col), strided
+// partial sums then a fixed-shape tree (deterministic)
+__global__ void __launch_bounds__(256) k_reduce_dots(int nvec, int nblk, int maxv, const double2* __restrict__ part,
+                                                     double2* __restrict__ h, int accumulate,
+                                                     const int* __restrict__ active) {
+  __shared__ double sh[8];
+  const int col = blockIdx.y, i = blockIdx.x;
   if (active && !active[col]) return;
-  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
-    double2 a = make_double2(0.0, 0.0);
-    for (int b = 0; b < nblk; ++b) a = cadd(a, part[((int64_t)col * nblk + b) * maxv + i]);
-    if (accumulate)
-      h[(int64_t)col * maxv + i] = cadd(h[(int64_t)col * maxv + i], a);
-    else
-      h[(int64_t)col * maxv + i] = a;
+  if (i >= nvec) return;
+  double sr = 0.0, si = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const double2 a = part[((int64_t)col * nblk + b) * maxv + i];
+    sr += a.x;
+    si += a.y;
+  }
+  sr = block_sum(sr, sh);
+  si = block_sum(si, sh);
+  if (threadIdx.x == 0) {
+    double2* o = h + (int64_t)col * maxv + i;
+    *o = accumulate ? make_double2(o->x + sr, o->y + si) : make_double2(sr, si);
   }
 }
 
@@ -455,8 +473,8 @@ void launch_local_solve(hipStream_t st, const LocalSolveArgs& a, const R* F, con
                         double2* z, int64_t zstride, double2* ys, int64_t ystride, int ncol, const int* active) {
   if (a.n_sub == 0 || ncol == 0) return;
   const size_t dyn = 2 * sizeof(R) * (size_t)a.max_ns;
-  hipLaunchKernelGGL((k_local_solve<R, kLuNB>), dim3(a.n_sub, ncol), dim3(256), dyn, st, F, a.foff, a.nsz, a.lds,
-                     a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, ys, ystride, active, a.order);
+  timed_launch(k_local_solve<R, kLuNB>, dim3(a.n_sub, ncol), dim3(256), (unsigned)dyn, st, F, a.foff, a.nsz, a.lds,
+               a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, ys, ystride, active, a.order);
 }
 template void launch_local_solve<double>(hipStream_t, const LocalSolveArgs&, const double*, const double2*, int64_t,
                                          double2*, int64_t, double2*, int64_t, int, const int*);
@@ -485,16 +503,16 @@ void launch_spmv(hipStream_t st, int group, int64_t n, const int64_t* rowptr, co
   const unsigned nb = (unsigned)((n * group + 255) / 256);
   switch (group) {
     case 4:
-      hipLaunchKernelGGL(k_spmv<4>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      timed_launch(k_spmv<4>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
       break;
     case 8:
-      hipLaunchKernelGGL(k_spmv<8>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      timed_launch(k_spmv<8>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
       break;
     case 16:
-      hipLaunchKernelGGL(k_spmv<16>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      timed_launch(k_spmv<16>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
       break;
     default:
-      hipLaunchKernelGGL(k_spmv<32>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
+      timed_launch(k_spmv<32>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
       break;
   }
 }
@@ -510,8 +528,8 @@ void launch_dots(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64
 
 void launch_reduce_dots(hipStream_t st, int64_t ndof, int nvec, const double2* part, double2* h, int maxv,
                         int accumulate, int ncol, const int* active) {
-  hipLaunchKernelGGL(k_reduce_dots, dim3(1, ncol), dim3(64), 0, st, nvec, red_blocks(ndof), maxv, part, h, accumulate,
-                     active);
+  hipLaunchKernelGGL(k_reduce_dots, dim3(nvec, ncol), dim3(256), 0, st, nvec, red_blocks(ndof), maxv, part, h,
+                     accumulate, active);
 }
 
 void launch_update(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64_t vcol, double2* w, int64_t wcol,
