@@ -172,6 +172,12 @@ mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64
 mxw_status mxw_problem_create_from_layout(const mxw_layout* layout, const double* eps, double k0,
                                           int32_t precision, int32_t prec_variant, void* stream,
                                           uint64_t hbm_budget, int32_t defer_factor, mxw_problem** out);
+/* Replaces the medium of an existing problem (eps [n_tets][2], NULL = the
+ * layout's; k0 < 0 keeps the current wavenumber) and redoes, in the problem's
+ * own device buffers, everything that depends on it: element matrices, CSR
+ * values, dense A_s and their LU factors (Sec. 2-4).  No device memory is
+ * allocated.  This is the step of an imaging loop, where only eps changes. */
+mxw_status mxw_problem_set_medium(mxw_problem* prob, const double* eps, double k0, void* stream);
 void mxw_problem_destroy(mxw_problem* prob);
 mxw_status mxw_problem_get_info(const mxw_problem* prob, mxw_layout_info* info);
 /* Factorises every A_s in place (batched LU, partial pivoting). Idempotent.
@@ -193,7 +199,8 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
 /* y = A x for nrhs device vectors [nrhs][ndof] complex128. */
 mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_dev, double* y_dev,
                                void* stream);
-/* z = M^{-1} v (ORAS: restrict, local LU solves, Boolean prolongation). */
+/* z = M^{-1} v (ORAS: restrict, local LU solves, Boolean prolongation).
+ * With nrhs >= 2 (ORAS) every factor strip is read once per 32 columns. */
 mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double* v_dev, double* z_dev,
                                   void* stream);
 

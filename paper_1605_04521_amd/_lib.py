@@ -88,6 +88,7 @@ _SIGS = {
                                        C.POINTER(C.c_void_p)]),
     "mxw_problem_create_from_layout": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
                                                    C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "mxw_problem_set_medium": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "mxw_problem_destroy": (None, [C.c_void_p]),
     "mxw_problem_get_info": (C.c_int32, [C.c_void_p, C.POINTER(LayoutInfo)]),
     "mxw_problem_factor": (C.c_int32, [C.c_void_p, C.c_void_p]),

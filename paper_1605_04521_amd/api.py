@@ -102,6 +102,16 @@ class Problem:
         """Problem on an existing layout's mesh and partition with a new medium."""
         return cls(layout=layout, eps=eps, k0=k0, precision=precision, variant=variant, **kw)
 
+    def set_medium(self, eps=None, k0: float = -1.0):
+        """New permittivity (and optionally k0): re-assemble and re-factorise in place."""
+        e = None
+        if eps is not None:
+            e = np.asarray(eps, dtype=np.complex128)
+            self._eps = np.ascontiguousarray(np.stack([e.real, e.imag], axis=1))
+            e = self._eps.ctypes.data
+        return B.check(B.lib().mxw_problem_set_medium(self.h, e, float(k0), _stream()),
+                       (B.MXW_OK, B.MXW_ESINGULAR))
+
     def close(self):
         """Release the device memory now (instead of at garbage collection)."""
         if getattr(self, "h", None) is not None and self.h.value:

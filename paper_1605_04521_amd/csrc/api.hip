@@ -212,6 +212,7 @@ struct KrylovWork {
   double2 *h1 = nullptr, *h2 = nullptr, *part = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double *cs = nullptr, *hn = nullptr, *w0 = nullptr, *npart = nullptr, *est = nullptr, *beta = nullptr;
   int *active = nullptr, *jd = nullptr;
+  void* xbuf = nullptr;     // multi-column local solve workspace
   double* host = nullptr;   // pinned: est, hn, w0 for every column
   std::vector<std::vector<double>> history;   // per column: |g_{j+1}| / ||b|| of every step
 };
@@ -404,6 +405,16 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
     set_error("Krylov workspace allocation failed");
     return MXW_ENOMEM;
   }
+  k.xbuf = nullptr;
+  if (nrhs >= 2 && P->variant == MXW_PREC_ORAS) {
+    const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
+    k.xbuf = k.mem.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() * (P->mixed ? 4 : 8));
+    if (!k.xbuf) {
+      k.V = nullptr;
+      set_error("Krylov workspace allocation failed (multi-column local solve)");
+      return MXW_ENOMEM;
+    }
+  }
   if (hipHostMalloc((void**)&k.host, sizeof(double) * 4 * nrhs) != hipSuccess) {
     set_error("pinned host allocation failed");
     return MXW_ENOMEM;
@@ -413,7 +424,19 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
 
 // z = M^{-1} v for ncol columns (device, stride ndof)
 void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vstride, double2* z, int64_t zstride,
-                    int ncol, const int* active, double2* ys) {
+                    int ncol, const int* active, double2* ys, void* xbuf = nullptr) {
+  if (xbuf && ncol >= 2 && P->variant == MXW_PREC_ORAS) {
+    ScopedKernelTimer tm("local_solve_multi");
+    LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
+                     P->order};
+    if (P->mixed)
+      launch_local_solve_multi<float>(st, a, (const float*)P->F, v, vstride, z, zstride, (float*)xbuf, P->L.sum_ns,
+                                      ncol, active);
+    else
+      launch_local_solve_multi<double>(st, a, (const double*)P->F, v, vstride, z, zstride, (double*)xbuf,
+                                       P->L.sum_ns, ncol, active);
+    return;
+  }
   ScopedKernelTimer tm("local_solve");
   LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
                    P->order};
@@ -709,6 +732,43 @@ mxw_status ensure_device_layout(LayoutShared& S, hipStream_t st) {
   return MXW_OK;
 }
 
+// Everything that depends on the medium, in the problem's existing buffers:
+// face coefficients, FP64 element matrices, CSR values, dense A_s and (unless
+// deferred) their LU factors.
+mxw_status assemble_medium(mxw_problem* P, const double* eps, double k0, hipStream_t st, int defer_factor) {
+  const Layout& L = P->L;
+  const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
+  std::vector<double> beta, coef, ie(2 * L.imp_tet.size());
+  face_coefficients(L, eps, k0, beta, coef);
+  for (size_t q = 0; q < L.imp_tet.size(); ++q) {
+    ie[2 * q] = eps[2 * (int64_t)L.imp_tet[q]];
+    ie[2 * q + 1] = eps[2 * (int64_t)L.imp_tet[q] + 1];
+  }
+  HIP_CHECK(hipMemcpyAsync(P->eps, eps, sizeof(double) * 2 * L.nt, hipMemcpyHostToDevice, st));
+  if (!beta.empty())
+    HIP_CHECK(hipMemcpyAsync(P->imp_beta, beta.data(), sizeof(double) * beta.size(), hipMemcpyHostToDevice, st));
+  if (!ie.empty()) HIP_CHECK(hipMemcpyAsync(P->imp_eps, ie.data(), sizeof(double) * ie.size(), hipMemcpyHostToDevice, st));
+  if (!coef.empty())
+    HIP_CHECK(hipMemcpyAsync(P->sub_face_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, st));
+  P->k0 = k0;
+  P->factored = false;
+  {
+    ScopedTimer tm(st, "assemble");
+    launch_element(st, L.nt, P->xyz, P->tets, P->eps, P->phi, P->curl, nloc, L.basis.ncurl_max, k0 * k0, P->AT);
+    AssembleArgs aa{L.ndof, P->rowptr, P->cols, P->dof_ent, P->ent_tet_ptr, P->ent_tets, P->ent_imp_ptr, P->ent_imps,
+                    P->tet_dofs, nloc, P->AT, P->imp_ft, P->imp_beta, P->ft_dofs, nfloc, P->BF, P->vals};
+    launch_assemble_rows(st, aa);
+  }
+  HIP_CHECK(hipGetLastError());
+  if (P->mixed)
+    TRY(build_local_and_factor<float>(P, st, false));
+  else
+    TRY(build_local_and_factor<double>(P, st, false));
+  HIP_CHECK(hipStreamSynchronize(st));   // the host vectors above go out of scope
+  if (defer_factor) return MXW_OK;
+  return factor_impl(P, st);
+}
+
 mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* eps_in, double k0, int precision,
                           int variant, hipStream_t st, uint64_t hbm_budget, int defer_factor, mxw_problem** out) {
   const Layout& L = S->L;
@@ -796,16 +856,10 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
   // medium-dependent data
   const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
   DevMem& M = P->mem;
-  std::vector<double> eps_v(eps, eps + 2 * L.nt), beta, coef, ie(2 * L.imp_tet.size());
-  face_coefficients(L, eps, k0, beta, coef);
-  for (size_t q = 0; q < L.imp_tet.size(); ++q) {
-    ie[2 * q] = eps[2 * (int64_t)L.imp_tet[q]];
-    ie[2 * q + 1] = eps[2 * (int64_t)L.imp_tet[q] + 1];
-  }
-  TRY(upload(M, P->eps, eps_v, st));
-  TRY(upload(M, P->imp_beta, beta, st));
-  TRY(upload(M, P->imp_eps, ie, st));
-  TRY(upload(M, P->sub_face_coef, coef, st));
+  P->eps = M.alloc<double>(2 * L.nt);
+  P->imp_beta = M.alloc<double>(L.imp_tet.size());
+  P->imp_eps = M.alloc<double>(2 * L.imp_tet.size());
+  P->sub_face_coef = M.alloc<double>(L.sub_face_tet.size());
   P->perm = M.alloc<int>(L.sum_ns);
   P->info = M.alloc<int>(L.n_sub);
   const size_t rsz = mixed ? 4 : 8;
@@ -813,7 +867,8 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
   P->lu_scratch = M.alloc<unsigned char>((size_t)L.n_sub * 2 * kLuNB * kLuNB * rsz);
   P->AT = M.alloc<double2>((size_t)L.nt * nloc * nloc);
   P->vals = M.alloc<double2>(L.cols.size());
-  if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->vals) {
+  if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->vals || !P->eps || !P->imp_beta ||
+      !P->imp_eps || !P->sub_face_coef) {
     set_error("device allocation failed (factors or element data)");
     return MXW_ENOMEM;
   }
@@ -821,27 +876,10 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
     const size_t dyn = 2 * (size_t)L.max_ns;
     HIP_CHECK(prepare_local_solve(dyn * 8, dyn * 4));
   }
-  // FP64 element matrices and CSR assembly of A
-  {
-    ScopedTimer tm(st, "assemble");
-    launch_element(st, L.nt, P->xyz, P->tets, P->eps, P->phi, P->curl, nloc, L.basis.ncurl_max, k0 * k0, P->AT);
-    AssembleArgs aa{L.ndof, P->rowptr, P->cols, P->dof_ent, P->ent_tet_ptr, P->ent_tets, P->ent_imp_ptr, P->ent_imps,
-                    P->tet_dofs, nloc, P->AT, P->imp_ft, P->imp_beta, P->ft_dofs, nfloc, P->BF, P->vals};
-    launch_assemble_rows(st, aa);
-  }
-  HIP_CHECK(hipGetLastError());
   const int64_t nnz_row = L.ndof ? L.rowptr.back() / L.ndof : 0;
   P->spmv_group = nnz_row <= 12 ? 4 : nnz_row <= 24 ? 8 : nnz_row <= 64 ? 16 : 32;
-  if (P->mixed)
-    TRY(build_local_and_factor<float>(P.get(), st, false));
-  else
-    TRY(build_local_and_factor<double>(P.get(), st, false));
-  HIP_CHECK(hipStreamSynchronize(st));
-  mxw_status result = MXW_OK;
-  if (!defer_factor) {
-    result = factor_impl(P.get(), st);
-    if (result != MXW_OK && result != MXW_ESINGULAR) return result;
-  }
+  mxw_status result = assemble_medium(P.get(), eps, k0, st, defer_factor);
+  if (result != MXW_OK && result != MXW_ESINGULAR) return result;
   *out = P.release();
   return result;
 }
@@ -879,6 +917,23 @@ mxw_status mxw_problem_create_from_layout(const mxw_layout* layout, const double
   *out = nullptr;
   return create_problem(layout->S, eps, k0 < 0 ? layout->S->L.k0 : k0, precision, prec_variant,
                         (hipStream_t)stream, hbm_budget, defer_factor, out);
+}
+
+mxw_status mxw_problem_set_medium(mxw_problem* prob, const double* eps, double k0, void* stream) {
+  TRY(check_problem(prob));
+  const Layout& L = prob->L;
+  if (!eps) eps = L.eps.data();
+  if (k0 < 0) k0 = prob->k0;
+  if (!std::isfinite(k0)) {
+    set_error("k0 must be finite and >= 0");
+    return MXW_EINVAL;
+  }
+  for (int64_t q = 0; q < 2 * L.nt; ++q)
+    if (!std::isfinite(eps[q])) {
+      set_error("non-finite permittivity");
+      return MXW_EINVAL;
+    }
+  return assemble_medium(prob, eps, k0, (hipStream_t)stream, 0);
 }
 
 void mxw_problem_destroy(mxw_problem* prob) {
@@ -1041,10 +1096,16 @@ mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double*
   }
   hipStream_t st = (hipStream_t)stream;
   double2* ys = nullptr;
+  void* xbuf = nullptr;
   if (prob->variant == MXW_PREC_OAS) HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
-  apply_prec_dev(prob, st, (const double2*)v_dev, prob->L.ndof, (double2*)z_dev, prob->L.ndof, nrhs, nullptr, ys);
+  if (prob->variant == MXW_PREC_ORAS && nrhs >= 2) {
+    const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
+    HIP_CHECK(hipMallocAsync(&xbuf, (size_t)nchunk * 2 * prob->L.sum_ns * multi_chunk_cols() * (prob->mixed ? 4 : 8), st));
+  }
+  apply_prec_dev(prob, st, (const double2*)v_dev, prob->L.ndof, (double2*)z_dev, prob->L.ndof, nrhs, nullptr, ys, xbuf);
   HIP_CHECK(hipGetLastError());
   if (ys) HIP_CHECK(hipFreeAsync(ys, st));
+  if (xbuf) HIP_CHECK(hipFreeAsync(xbuf, st));
   HIP_CHECK(hipStreamSynchronize(st));
   return MXW_OK;
 }
@@ -1118,7 +1179,7 @@ mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, cons
       double2* Vj = k.V + (int64_t)j * n;
       double2* Zj = k.Z + (int64_t)j * n;
       // z_j = M^{-1} v_j (columns at stride vcol / zcol)
-      apply_prec_dev(P, st, Vj, vcol, Zj, zcol, nrhs, k.active, k.YS);
+      apply_prec_dev(P, st, Vj, vcol, Zj, zcol, nrhs, k.active, k.YS, k.xbuf);
       {
         ScopedKernelTimer tm("spmv");
         launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, zcol, k.W, n, nullptr, 0, nrhs, k.active);

@@ -141,18 +141,61 @@ def test_end_to_end_mixed(name):
     assert it[0] <= it_o + 10
 
 
-def test_pseudo_block_columns_equal_single():
+def test_pseudo_block_columns_match_single():
     """Several right-hand sides in one launch sequence give, column by column,
-    exactly the single right-hand side results (same alone and in the mix)."""
+    the single right-hand side results: the Krylov arithmetic of a column is
+    the same; the batched local solve sums in MFMA order, so E agrees to
+    rounding and the iteration counts agree."""
     prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2, n_sources=4)
     say("[gpu] pseudo-block 4 columns vs single")
     P = Problem.from_problem(prob)
     X, it, rr, _ = P.solve(prob.sources)
     X = to_np(X)
+    orc = OracleSolver.from_problem(prob)
     for c in range(4):
         x1, it1, rr1, _ = P.solve(prob.sources[c:c + 1])
-        assert it1[0] == it[c]
-        assert np.array_equal(to_np(x1)[0], X[c]), c
+        assert abs(int(it1[0]) - int(it[c])) <= 1 and rr[c] <= 1e-8
+        x1 = to_np(x1)[0]
+        assert np.linalg.norm(x1 - X[c]) <= 1e-7 * np.linalg.norm(x1), c
+        xo, ito, _, _ = orc.solve(orc.rhs(prob.sources[c]))
+        assert np.linalg.norm(X[c] - xo) <= 1e-6 * np.linalg.norm(xo), c
+
+
+@pytest.mark.parametrize("precision", [B.MXW_FP64, B.MXW_MIXED])
+@pytest.mark.parametrize("ncol", [5, 33])
+def test_multi_column_local_solve(precision, ncol):
+    """The all-columns ORAS kernel (factor strips read once per 32 columns,
+    MFMA products) equals the one-column kernel to rounding, including a ragged
+    column chunk and a second chunk."""
+    prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2)
+    say(f"[gpu] multi-column ORAS precision={precision} ncol={ncol}")
+    P = Problem.from_problem(prob, precision=precision)
+    rng = np.random.default_rng(11)
+    V = rng.standard_normal((ncol, P.ndof)) + 1j * rng.standard_normal((ncol, P.ndof))
+    # several columns go through the batched kernel, one column through the
+    # one-column kernel
+    Vt = torch.from_numpy(V).cuda()
+    Zb = to_np(P.apply_prec(Vt))
+    tol = 1e-12 if precision == B.MXW_FP64 else 1e-5
+    for c in range(ncol):
+        z1 = to_np(P.apply_prec(Vt[c:c + 1]))[0]
+        assert np.linalg.norm(Zb[c] - z1) <= tol * np.linalg.norm(z1), c
+
+
+def test_set_medium_equals_fresh_problem():
+    prob = gen.chamber_problem(n=5, degree=2, n_sub=6, overlap=2, seed=1)
+    prob2 = gen.chamber_problem(n=5, degree=2, n_sub=6, overlap=2, seed=2)
+    say("[gpu] set_medium vs fresh problem")
+    P = Problem.from_problem(prob)
+    x1, it1, rr1, _ = P.solve(prob.sources[:1])
+    P.set_medium(prob2.eps)
+    Q = Problem.from_problem(prob2)
+    assert np.array_equal(P.matrix_values(), Q.matrix_values())
+    xp, itp, _, _ = P.solve(prob2.sources[:1])
+    xq, itq, _, _ = Q.solve(prob2.sources[:1])
+    assert itp[0] == itq[0]
+    assert np.array_equal(to_np(xp), to_np(xq))
+    assert not np.allclose(to_np(x1), to_np(xp))
 
 
 def test_oas_variant_converges_slower():
