@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each Arnoldi step as a captured HIP graph (kernel timers are off inside graphs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -277,7 +279,7 @@ def main():
         P = holder["P"]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, it, rr, st = P.solve(prob.sources[:args.nrhs])
+        x, it, rr, st = P.solve(prob.sources[:args.nrhs], use_graph=int(args.graph))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         phases.append((t1 - t0, t2 - t1))
@@ -358,7 +360,7 @@ def main():
         "vs_baseline": None, "dtype": "f64" if precision == B.MXW_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": wl, "ndof": int(info.ndof), "nnz": int(info.nnz), "n_sub": int(info.n_sub),
                    "max_ns": int(info.max_ns), "nrhs": args.nrhs, "precision": args.precision,
-                   "iterations": iters, "restart": 50, "tol": 1e-8},
+                   "iterations": iters, "restart": 50, "tol": 1e-8, "graph": bool(args.graph)},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "mesh_setup_s": t_mesh,
         "phase_s": {"assemble_factor": float(np.median([p[0] for p in phases[-args.steps:]])),

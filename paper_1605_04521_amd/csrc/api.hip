@@ -31,6 +31,7 @@ struct TimingRec {
 };
 static std::mutex g_tmu;
 static bool g_timing = false;
+static thread_local bool g_capturing = false;   // no timers inside a captured graph
 static std::vector<TimingRec> g_pending;
 static std::vector<hipEvent_t> g_event_pool;   // events reused across launches
 static std::map<std::string, std::pair<double, int64_t>> g_totals;
@@ -53,7 +54,7 @@ struct ScopedTimer {
   const char* name;
   hipEvent_t a = nullptr, b = nullptr;
   ScopedTimer(hipStream_t s, const char* n) : st(s), name(n) {
-    if (!g_timing) return;
+    if (!g_timing || g_capturing) return;
     a = pooled_event();
     b = pooled_event();
     if (!a || !b) {
@@ -91,7 +92,7 @@ struct ScopedKernelTimer {
   const char* name;
   KernelEvents ev;
   explicit ScopedKernelTimer(const char* n) : name(n) {
-    if (!g_timing) return;
+    if (!g_timing || g_capturing) return;
     ev.a = pooled_event();
     ev.b = pooled_event();
     if (!ev.a || !ev.b) {
@@ -214,6 +215,19 @@ struct KrylovWork {
   int *active = nullptr, *jd = nullptr;
   void* xbuf = nullptr;     // multi-column local solve workspace
   double* host = nullptr;   // pinned: est, hn, w0 for every column
+  std::vector<hipGraphExec_t> graphs;   // captured Arnoldi step per index j
+  int graph_nrhs = 0;                   // column count the graphs were captured for
+  hipStream_t cap = nullptr;            // private capture stream
+  void drop_graphs() {
+    for (auto& e : graphs)
+      if (e) hipGraphExecDestroy(e);
+    graphs.clear();
+    graph_nrhs = 0;
+  }
+  ~KrylovWork() {
+    drop_graphs();
+    if (cap) hipStreamDestroy(cap);
+  }
   std::vector<std::vector<double>> history;   // per column: |g_{j+1}| / ||b|| of every step
 };
 
@@ -366,6 +380,7 @@ uint64_t base_bytes(const Layout& L) {
 mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   KrylovWork& k = P->kw;
   if (k.nrhs >= nrhs && k.m == m && k.ndof == P->L.ndof && k.V) return MXW_OK;
+  k.drop_graphs();
   k.mem.reset();
   if (k.host) {
     hipHostFree(k.host);
@@ -1179,23 +1194,58 @@ mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, cons
       double2* Vj = k.V + (int64_t)j * n;
       double2* Zj = k.Z + (int64_t)j * n;
       // z_j = M^{-1} v_j (columns at stride vcol / zcol)
-      apply_prec_dev(P, st, Vj, vcol, Zj, zcol, nrhs, k.active, k.YS, k.xbuf);
-      {
-        ScopedKernelTimer tm("spmv");
-        launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, zcol, k.W, n, nullptr, 0, nrhs, k.active);
-      }
-      {
-        launch_norm(st, n, k.W, n, k.npart, k.w0, nrhs, k.active);
-        launch_dots(st, n, j + 1, k.V, vcol, k.W, n, k.part, maxv, nrhs, k.active);
-        launch_reduce_dots(st, n, j + 1, k.part, k.h1, maxv, 0, nrhs, k.active);
-        launch_update(st, n, j + 1, k.V, vcol, k.W, n, k.h1, maxv, nrhs, k.active);
-        launch_dots(st, n, j + 1, k.V, vcol, k.W, n, k.part, maxv, nrhs, k.active);
-        launch_reduce_dots(st, n, j + 1, k.part, k.h2, maxv, 0, nrhs, k.active);
-        launch_update(st, n, j + 1, k.V, vcol, k.W, n, k.h2, maxv, nrhs, k.active);
-        launch_reduce_dots(st, n, j + 1, k.part, k.h1, maxv, 1, nrhs, k.active);   // h1 += h2
-        launch_norm(st, n, k.W, n, k.npart, k.hn, nrhs, k.active);
-        launch_givens(st, nrhs, j, maxv, k.h1, k.hn, k.H, m, k.cs, k.sn, k.g, k.est, k.active);
-        launch_scale_inv(st, n, k.W, n, k.V + (int64_t)(j + 1) * n, vcol, k.hn, nrhs, k.active);
+      // one Arnoldi step: z_j = M^{-1} v_j, w = A z_j, CGS2, ||w||, Givens, v_{j+1}
+      auto step = [&](hipStream_t s) {
+        apply_prec_dev(P, s, Vj, vcol, Zj, zcol, nrhs, k.active, k.YS, k.xbuf);
+        {
+          ScopedKernelTimer tm("spmv");
+          launch_spmv(s, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, zcol, k.W, n, nullptr, 0, nrhs,
+                      k.active);
+        }
+        launch_norm(s, n, k.W, n, k.npart, k.w0, nrhs, k.active);
+        launch_dots(s, n, j + 1, k.V, vcol, k.W, n, k.part, maxv, nrhs, k.active);
+        launch_reduce_dots(s, n, j + 1, k.part, k.h1, maxv, 0, nrhs, k.active);
+        launch_update(s, n, j + 1, k.V, vcol, k.W, n, k.h1, maxv, nrhs, k.active);
+        launch_dots(s, n, j + 1, k.V, vcol, k.W, n, k.part, maxv, nrhs, k.active);
+        launch_reduce_dots(s, n, j + 1, k.part, k.h2, maxv, 0, nrhs, k.active);
+        launch_update(s, n, j + 1, k.V, vcol, k.W, n, k.h2, maxv, nrhs, k.active);
+        launch_reduce_dots(s, n, j + 1, k.part, k.h1, maxv, 1, nrhs, k.active);   // h1 += h2
+        launch_norm(s, n, k.W, n, k.npart, k.hn, nrhs, k.active);
+        launch_givens(s, nrhs, j, maxv, k.h1, k.hn, k.H, m, k.cs, k.sn, k.g, k.est, k.active);
+        launch_scale_inv(s, n, k.W, n, k.V + (int64_t)(j + 1) * n, vcol, k.hn, nrhs, k.active);
+      };
+      if (opts->use_graph) {
+        // The step of index j is captured once per workspace and column count
+        // and replayed: every argument is a fixed device address, a size or j;
+        // the changing state (active columns, H, g) lives in device memory.
+        // Capture runs on a private stream (the caller's may be the legacy
+        // default stream, which cannot capture); replay runs on the caller's.
+        if (k.graph_nrhs != nrhs) {
+          k.drop_graphs();
+          k.graph_nrhs = nrhs;
+        }
+        if ((int)k.graphs.size() < m) k.graphs.resize(m, nullptr);
+        if (!k.graphs[j]) {
+          if (!k.cap) HIP_CHECK(hipStreamCreateWithFlags(&k.cap, hipStreamNonBlocking));
+          hipGraph_t g = nullptr;
+          g_capturing = true;
+          hipError_t ce = hipStreamBeginCapture(k.cap, hipStreamCaptureModeThreadLocal);
+          if (ce == hipSuccess) {
+            step(k.cap);
+            ce = hipStreamEndCapture(k.cap, &g);
+          }
+          g_capturing = false;
+          if (ce != hipSuccess) return dev_fail("graph capture", ce);
+          const hipError_t ie = hipGraphInstantiate(&k.graphs[j], g, nullptr, nullptr, 0);
+          hipGraphDestroy(g);
+          if (ie != hipSuccess) {
+            k.graphs[j] = nullptr;
+            return dev_fail("hipGraphInstantiate", ie);
+          }
+        }
+        HIP_CHECK(hipGraphLaunch(k.graphs[j], st));
+      } else {
+        step(st);
       }
       HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipMemcpyAsync(hbuf, k.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));

@@ -243,6 +243,65 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t* __restri
   }
 }
 
+// Several columns at once (the products of all right-hand sides fused, Sec. 5):
+// a group of G lanes owns a row and CB columns, so every matrix entry and
+// column index is read once per CB columns instead of once per column.  Each
+// column is summed in the same lane order and shuffle tree as k_spmv.
+template <int G, int CB>
+__global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restrict__ rowptr, const int* __restrict__ cols,
+                                              const double2* __restrict__ vals, const double2* __restrict__ x,
+                                              int64_t xstride, double2* __restrict__ y, int64_t ystride,
+                                              const double2* __restrict__ b, int64_t bstride, int ncol,
+                                              const int* __restrict__ active) {
+  const int c0 = blockIdx.y * CB;
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x % G;
+  if (row >= n) return;
+  bool on[CB];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    on[q] = c0 + q < ncol && (!active || active[c0 + q]);
+    any |= on[q];
+  }
+  if (!any) return;
+  double sr[CB], si[CB];
+#pragma unroll
+  for (int q = 0; q < CB; ++q) sr[q] = si[q] = 0.0;
+  const int64_t r0 = rowptr[row], r1 = rowptr[row + 1];
+  for (int64_t c = r0 + l; c < r1; c += G) {
+    const double2 a = vals[c];
+    const int64_t j = cols[c];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      if (!on[q]) continue;
+      const double2 xv = x[(int64_t)(c0 + q) * xstride + j];
+      sr[q] += a.x * xv.x - a.y * xv.y;
+      si[q] += a.x * xv.y + a.y * xv.x;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+      sr[q] += __shfl_xor(sr[q], o, G);
+      si[q] += __shfl_xor(si[q], o, G);
+    }
+  }
+  if (l != 0) return;
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    if (!on[q]) continue;
+    const int col = c0 + q;
+    if (b) {
+      const double2 bv = b[(int64_t)col * bstride + row];
+      y[(int64_t)col * ystride + row] = make_double2(bv.x - sr[q], bv.y - si[q]);
+    } else {
+      y[(int64_t)col * ystride + row] = make_double2(sr[q], si[q]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Krylov vector kernels.  Column c of the batch uses V + c*vcol, where
 // vector i of the basis is at offset i*ndof.
@@ -496,24 +555,30 @@ void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const i
                      ystride, z, zstride, active);
 }
 
+constexpr int kSpmmCols = 8;   // columns per k_spmm group
+
+template <int G>
+static void spmv_g(hipStream_t st, unsigned nb, int64_t n, const int64_t* rowptr, const int* cols,
+                   const double2* vals, const double2* x, int64_t xstride, double2* y, int64_t ystride,
+                   const double2* b, int64_t bstride, int ncol, const int* active) {
+  if (ncol == 1)
+    timed_launch(k_spmv<G>, dim3(nb, 1), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride,
+                 active);
+  else
+    timed_launch(k_spmm<G, kSpmmCols>, dim3(nb, (ncol + kSpmmCols - 1) / kSpmmCols), dim3(256), 0, st, n, rowptr,
+                 cols, vals, x, xstride, y, ystride, b, bstride, ncol, active);
+}
+
 void launch_spmv(hipStream_t st, int group, int64_t n, const int64_t* rowptr, const int* cols, const double2* vals,
                  const double2* x, int64_t xstride, double2* y, int64_t ystride, const double2* b, int64_t bstride,
                  int ncol, const int* active) {
   if (n == 0 || ncol == 0) return;
   const unsigned nb = (unsigned)((n * group + 255) / 256);
   switch (group) {
-    case 4:
-      timed_launch(k_spmv<4>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
-      break;
-    case 8:
-      timed_launch(k_spmv<8>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
-      break;
-    case 16:
-      timed_launch(k_spmv<16>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
-      break;
-    default:
-      timed_launch(k_spmv<32>, dim3(nb, ncol), dim3(256), 0, st, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, active);
-      break;
+    case 4: spmv_g<4>(st, nb, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, ncol, active); break;
+    case 8: spmv_g<8>(st, nb, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, ncol, active); break;
+    case 16: spmv_g<16>(st, nb, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, ncol, active); break;
+    default: spmv_g<32>(st, nb, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, ncol, active); break;
   }
 }
 
