@@ -8,7 +8,8 @@
 // row of X is contiguous) lives in a global scratch buffer.  Forward sweep over
 // 32-row blocks b:  T_b = X_b - L_{b,<b} X_{<b}  (MFMA, K = rows before b),
 // X_b = L_bb^{-1} T_b (the diagonal block holds L_bb^{-1}); backward likewise
-// with U and U_bb^{-1}.  Each wave owns a 16 x 16 tile (rows x columns) of T_b.
+// with U and U_bb^{-1}.  The K range of each product is split over the four
+// waves, whose 32 x 32 partial products are summed in LDS.
 #include "device.h"
 #include "kernels.h"
 
@@ -25,7 +26,8 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
     const int* __restrict__ active, const int* __restrict__ order) {
   static_assert(NB == 32 && PC == 32, "tile shape assumes 32 x 32 blocks");
   typedef typename Mfma<R>::acc_t acc_t;
-  __shared__ R Tr[NB][PC + 1], Ti[NB][PC + 1];     // T_b
+  // Sr/Si[2]: partial products of the waves, then T_b in slot 0
+  __shared__ R Sr[2][NB][PC + 1], Si[2][NB][PC + 1];
   __shared__ R Dr[NB][NB + 1], Di[NB][NB + 1];     // diagonal inverse block [row][col]
   const int s = order ? order[blockIdx.x] : blockIdx.x;
   const int chunk = blockIdx.y, c0 = chunk * PC;
@@ -38,7 +40,7 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
   R* Xr = xbuf + (int64_t)chunk * xchunk + 2 * poff[s] * PC;
   R* Xi = Xr + (int64_t)n * PC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rb = wave & 1, cb = wave >> 1, li = lane & 15, lk = lane >> 4;
+  const int li = lane & 15, lk = lane >> 4;
 
   for (int idx = tid; idx < n * PC; idx += 256) {
     const int i = idx / PC, c = idx % PC, col = c0 + c;
@@ -54,42 +56,85 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
     for (int bq = 0; bq < nblk; ++bq) {
       const int b = sweep == 0 ? bq : nblk - 1 - bq;
       const int b0 = b * NB, bn = min(NB, n - b0);
-      // K range: [0, b0) forward, [b0 + bn, n) backward
+      // K range: [0, b0) forward, [b0 + bn, n) backward, split over the
+      // waves in 32-wide slices (slice q goes to wave q mod 4); every wave
+      // forms the whole 32 x 32 partial product of its slices, so each
+      // factor entry and each entry of X is loaded once per workgroup
       const int k_lo = sweep == 0 ? 0 : b0 + bn, k_hi = sweep == 0 ? b0 : n;
-      acc_t dre = acc_t{0, 0, 0, 0}, dim = acc_t{0, 0, 0, 0};
-      const int row = b0 + rb * 16 + li;
-      const bool row_ok = row < n;
-      const int col = cb * 16 + li;
-      for (int k0 = k_lo; k0 < k_hi; k0 += 32) {
-        R ar[8], ai[8], br[8], bi[8];
+      acc_t pre[2][2], pim[2][2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          pre[rt][ct] = acc_t{0, 0, 0, 0};
+          pim[rt][ct] = acc_t{0, 0, 0, 0};
+        }
+      bool row_ok[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) row_ok[rt] = rt * 16 + li < bn;
+      for (int k0 = k_lo + 32 * wave; k0 < k_hi; k0 += 128) {
+        R ar[2][8], ai[2][8], xr[2][8], xi[2][8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int kk = k0 + 4 * u + lk;
           const bool ok = kk < k_hi;
-          ar[u] = (ok && row_ok) ? Ar[(int64_t)kk * ld + row] : R(0);
-          ai[u] = (ok && row_ok) ? Ai[(int64_t)kk * ld + row] : R(0);
-          br[u] = ok ? Xr[(int64_t)kk * PC + col] : R(0);
-          bi[u] = ok ? Xi[(int64_t)kk * PC + col] : R(0);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) {
+            const int64_t o = (int64_t)kk * ld + b0 + rt * 16 + li;
+            ar[rt][u] = (ok && row_ok[rt]) ? Ar[o] : R(0);
+            ai[rt][u] = (ok && row_ok[rt]) ? Ai[o] : R(0);
+          }
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const int64_t o = (int64_t)kk * PC + ct * 16 + li;
+            xr[ct][u] = ok ? Xr[o] : R(0);
+            xi[ct][u] = ok ? Xi[o] : R(0);
+          }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          dre = Mfma<R>::op(ar[u], br[u], dre);
-          dre = Mfma<R>::op(-ai[u], bi[u], dre);
-          dim = Mfma<R>::op(ar[u], bi[u], dim);
-          dim = Mfma<R>::op(ai[u], br[u], dim);
-        }
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+              pre[rt][ct] = Mfma<R>::op(ar[rt][u], xr[ct][u], pre[rt][ct]);
+              pre[rt][ct] = Mfma<R>::op(-ai[rt][u], xi[ct][u], pre[rt][ct]);
+              pim[rt][ct] = Mfma<R>::op(ar[rt][u], xi[ct][u], pim[rt][ct]);
+              pim[rt][ct] = Mfma<R>::op(ai[rt][u], xr[ct][u], pim[rt][ct]);
+            }
       }
-      // T_b = X_b - (L or U) X ; stage the inverse diagonal block
+      // sum the four partial products: waves 0,1 store, waves 2,3 add
+      for (int phase = 0; phase < 2; ++phase) {
+        if ((wave >> 1) == phase) {
+          const int slot = wave & 1;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = rb * 16 + Mfma<R>::row(lane, q), c = cb * 16 + li;
-        R xr = R(0), xi = R(0);
-        if (r < bn) {
-          xr = Xr[(int64_t)(b0 + r) * PC + c];
-          xi = Xi[(int64_t)(b0 + r) * PC + c];
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int r = rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
+                if (phase == 0) {
+                  Sr[slot][r][c] = pre[rt][ct][q];
+                  Si[slot][r][c] = pim[rt][ct][q];
+                } else {
+                  Sr[slot][r][c] += pre[rt][ct][q];
+                  Si[slot][r][c] += pim[rt][ct][q];
+                }
+              }
         }
-        Tr[r][c] = xr - dre[q];
-        Ti[r][c] = xi - dim[q];
+        __syncthreads();
+      }
+      // T_b = X_b - (L or U) X in slot 0; stage the inverse diagonal block
+      for (int idx = tid; idx < NB * PC; idx += 256) {
+        const int r = idx / PC, c = idx % PC;
+        R tr = R(0), ti = R(0);
+        if (r < bn) {
+          tr = Xr[(int64_t)(b0 + r) * PC + c] - (Sr[0][r][c] + Sr[1][r][c]);
+          ti = Xi[(int64_t)(b0 + r) * PC + c] - (Si[0][r][c] + Si[1][r][c]);
+        }
+        Sr[0][r][c] = tr;
+        Si[0][r][c] = ti;
       }
       for (int idx = tid; idx < NB * NB; idx += 256) {
         const int r = idx % NB, c = idx / NB;
@@ -108,18 +153,18 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
         if (r >= bn) continue;
         R yr, yi;
         if (sweep == 0) {
-          yr = Tr[r][c];
-          yi = Ti[r][c];
+          yr = Sr[0][r][c];
+          yi = Si[0][r][c];
           for (int q = 0; q < r; ++q) {
-            yr += Dr[r][q] * Tr[q][c] - Di[r][q] * Ti[q][c];
-            yi += Dr[r][q] * Ti[q][c] + Di[r][q] * Tr[q][c];
+            yr += Dr[r][q] * Sr[0][q][c] - Di[r][q] * Si[0][q][c];
+            yi += Dr[r][q] * Si[0][q][c] + Di[r][q] * Sr[0][q][c];
           }
         } else {
           yr = R(0);
           yi = R(0);
           for (int q = r; q < bn; ++q) {
-            yr += Dr[r][q] * Tr[q][c] - Di[r][q] * Ti[q][c];
-            yi += Dr[r][q] * Ti[q][c] + Di[r][q] * Tr[q][c];
+            yr += Dr[r][q] * Sr[0][q][c] - Di[r][q] * Si[0][q][c];
+            yi += Dr[r][q] * Si[0][q][c] + Di[r][q] * Sr[0][q][c];
           }
         }
         Xr[(int64_t)(b0 + r) * PC + c] = yr;
