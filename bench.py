@@ -49,20 +49,21 @@ def kernel_source_hash(name):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, precision):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken with the current kernel source; else None."""
+KERNEL_SOURCES = {"lu": "lu_kernels.hip", "local_solve": "solve_kernels.hip", "spmv": "solve_kernels.hip",
+                  "local_solve_multi": "multi_solve.hip"}
+
+
+def measured_traffic(kernel, precision, nrhs):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), if it was taken
+    with the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
-    key = f"{kernel}|{workload}|{precision}"
-    rec = data.get(key)
-    if not rec:
-        return None
-    src = {"lu": "lu_kernels.hip", "local_solve": "solve_kernels.hip"}.get(kernel)
-    if src and rec.get("source_hash") != kernel_source_hash(src):
+    rec = data.get(f"{kernel}|{precision}|{nrhs}")
+    if not rec or rec.get("source_hash") != kernel_source_hash(KERNEL_SOURCES[kernel]):
         return None
     return rec.get("bytes_per_launch")
 
@@ -73,9 +74,15 @@ def cpu_baseline(prob, iters, n_sample_sub=12, seed=0):
     Timed fully: the oracle's global setup (entities, numbering, element
     matrices, global matrix) and one SpMV.  Sampled: local matrix assembly,
     sparse LU and one local solve for n_sample_sub random subdomains; scaled
-    by the number of subdomains.  One solve = setup + N_sub * local setup +
+    by the number of subdomains.  Runs on one host thread.  One solve = setup + N_sub * local setup +
     iters * (N_sub * local solve + SpMV); the Gram-Schmidt vector work is not
     counted (a lower bound on the oracle's time)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(prob, iters, n_sample_sub, seed)
+
+
+def _cpu_baseline(prob, iters, n_sample_sub, seed):
     import scipy.sparse.linalg as spla
     from oracle.assemble import Discretization
     from oracle.schwarz import Subdomain, grow_overlap, local_matrix, owners
@@ -115,7 +122,7 @@ def cpu_baseline(prob, iters, n_sample_sub=12, seed=0):
         t_apply.append(time.perf_counter() - t0)
     n = prob.n_sub
     per_solve = t_global + n * float(np.mean(t_setup)) + iters * (n * float(np.mean(t_apply)) + t_spmv)
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = 1   # BLAS pools limited to one thread; SciPy's sparse products and SuperLU are serial
     return {
         "value": 1.0 / per_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
         "sample": (f"oracle global setup + 1 SpMV timed in full ({t_global:.1f} s, {t_spmv:.3f} s); local "
@@ -124,6 +131,102 @@ def cpu_baseline(prob, iters, n_sample_sub=12, seed=0):
                    f"subdomains and {iters} GMRES iterations; orthogonalisation not counted"),
         "seconds_per_solve": per_solve,
     }
+
+
+def build_workload(args):
+    """The seeded problem and its host layout (entities, CSR pattern,
+    overlapping subdomains), built once per mesh."""
+    from paper_1605_04521_amd import gen
+    from paper_1605_04521_amd.api import Layout
+    t0 = time.perf_counter()
+    if args.workload == "cube":
+        prob = gen.cube_planewave_problem(n=args.n, degree=args.degree, seed=args.seed, n_sources=args.nrhs)
+        wl = f"unit cube {args.n}^3 Kuhn, r={args.degree}, plane wave, 2x2x2 boxes"
+    else:
+        nsub = tuple(int(q) for q in args.nsub.split("x")) if "x" in args.nsub else int(args.nsub)
+        prob = gen.chamber_problem(n=args.n, nz=args.nz, degree=args.degree, n_sub=nsub, overlap=args.overlap,
+                                   seed=args.seed, n_sources=args.nrhs)
+        kind = f"{args.nsub}-cell block-aligned" if "x" in args.nsub else "RCB"
+        wl = (f"imaging chamber cylinder R=0.15 m H=0.28 m, O-grid {args.n}x{args.n // 2}x{args.nz}, "
+              f"r={args.degree}, {prob.n_sub} {kind} subdomains, {args.overlap} face layers, "
+              f"{args.nrhs} dipole(s), eps 44+20i / head 40+15i / inclusion")
+    lay = Layout.from_problem(prob)
+    info = lay.info()
+    t_mesh = time.perf_counter() - t0
+    log(f"[bench] {wl}: ndof={info.ndof} nnz={info.nnz} n_sub={info.n_sub} max_ns={info.max_ns} "
+        f"sum_ns2={info.sum_ns2:.3e} host setup {t_mesh:.1f}s")
+    return prob, lay, info, wl, t_mesh
+
+
+def kernel_rooflines(info, precision, nrhs):
+    """Per-kernel achieved rates from the in-dispatch HIP-event timers:
+    algorithmic bytes or flops per launch / average launch duration."""
+    from paper_1605_04521_amd import _lib as B
+    from paper_1605_04521_amd.api import kernel_time
+    ktimes = {}
+    for name in ("lu", "local_solve", "local_solve_multi", "spmv"):
+        ktimes[name] = kernel_time(name)
+    rsz = 8 if precision == B.MXW_FP64 else 4
+    mfma_peak = FP64_PEAK_TFLOPS if precision == B.MXW_FP64 else FP32_PEAK_TFLOPS
+    lu_flops = 8.0 / 3.0 * info.sum_ns3            # complex LU: 8 n^3 / 3 real flops
+    # one column: every factor entry once (2 planes), restrict + prolong vectors
+    solve_bytes = 2 * rsz * info.sum_ns2 + 16 * info.sum_ns * 2 + 16 * info.ndof * 2
+    kern = {}
+
+    def add(name, bound, amount, peak, unit, **extra):
+        ms, n = ktimes[name]
+        if not n:
+            return
+        avg = ms / n / 1e3
+        kern[name] = dict(bound=bound, achieved=amount / avg / (1e12 if unit == "TFLOP/s" else 1e9), peak=peak,
+                          unit=unit, avg_ms=avg * 1e3, launches=n, total_ms=ms, **extra)
+
+    add("lu", "mfma", lu_flops, mfma_peak, "TFLOP/s")
+    add("local_solve", "hbm", nrhs * solve_bytes, HBM_PEAK_GBS, "GB/s")
+    # all columns of a 32-column chunk per factor read: MFMA-bound at 32 columns
+    add("local_solve_multi", "mfma", 8.0 * info.sum_ns2 * nrhs, mfma_peak, "TFLOP/s")
+    if "local_solve_multi" in kern:
+        k = kern["local_solve_multi"]
+        k["factor_GBps"] = 2 * rsz * info.sum_ns2 / (k["avg_ms"] / 1e3) / 1e9
+    # matrix once (16 B value + 4 B index per entry, row pointers), x read and y written per column
+    add("spmv", "hbm", 20 * info.nnz + 8 * (info.ndof + 1) + 32 * info.ndof * nrhs, HBM_PEAK_GBS, "GB/s")
+    for v in kern.values():
+        v["frac"] = v["achieved"] / v["peak"]
+    return kern
+
+
+def kernels_probe(args):
+    """Each hot kernel launched a few times on the chamber workload (no
+    solve): the LU of every A_s once, then --steps applications of ORAS and
+    of A to --nrhs random columns; then a 1 GiB device copy, whose counter
+    readings calibrate FETCH_SIZE / WRITE_SIZE.  Meant to run under
+    rocprofv3; prints one JSON line with the HIP-event kernel timings."""
+    import torch
+    from paper_1605_04521_amd import _lib as B
+    from paper_1605_04521_amd.api import Problem, reset_timing, timing
+    precision = B.MXW_FP64 if args.precision == "fp64" else B.MXW_MIXED
+    prob, lay, info, wl, _ = build_workload(args)
+    timing(True)
+    reset_timing()
+    P = Problem.from_layout(lay, eps=prob.eps, k0=prob.k0, precision=precision)
+    g = torch.Generator(device="cuda").manual_seed(args.seed)
+    V = torch.complex(torch.randn(args.nrhs, info.ndof, dtype=torch.float64, device="cuda", generator=g),
+                      torch.randn(args.nrhs, info.ndof, dtype=torch.float64, device="cuda", generator=g))
+    for i in range(args.steps):
+        P.apply_prec(V)
+        P.apply_A(V)
+        log(f"[kernels] application {i} done")
+    torch.cuda.synchronize()
+    timing(False)
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    out = {"workload": "kernels", "config": wl, "precision": args.precision, "nrhs": args.nrhs,
+           "applications": args.steps, "copy_bytes": 1 << 30,
+           "kernels": kernel_rooflines(info, precision, args.nrhs),
+           "source_hash": {k: kernel_source_hash(v) for k, v in KERNEL_SOURCES.items()}}
+    print(json.dumps(out), flush=True)
 
 
 def serve_bench(args):
@@ -206,7 +309,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chamber", choices=["chamber", "cube", "serve"])
+    ap.add_argument("--workload", default="chamber", choices=["chamber", "cube", "serve", "kernels"])
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--baseline-requests", type=int, default=3)
     ap.add_argument("--budget-gb", type=float, default=250.0)
@@ -242,25 +345,12 @@ def main():
     if args.workload == "serve":
         serve_bench(args)
         return
+    if args.workload == "kernels":
+        kernels_probe(args)
+        return
     precision = B.MXW_FP64 if args.precision == "fp64" else B.MXW_MIXED
 
-    t0 = time.perf_counter()
-    if args.workload == "chamber":
-        nsub = tuple(int(q) for q in args.nsub.split("x")) if "x" in args.nsub else int(args.nsub)
-        prob = gen.chamber_problem(n=args.n, nz=args.nz, degree=args.degree, n_sub=nsub, overlap=args.overlap,
-                                   seed=args.seed, n_sources=args.nrhs)
-        kind = f"{args.nsub}-cell block-aligned" if "x" in args.nsub else "RCB"
-        wl = (f"imaging chamber cylinder R=0.15 m H=0.28 m, O-grid {args.n}x{args.n // 2}x{args.nz}, "
-              f"r={args.degree}, {prob.n_sub} {kind} subdomains, {args.overlap} face layers, "
-              f"{args.nrhs} dipole(s), eps 44+20i / head 40+15i / inclusion")
-    else:
-        prob = gen.cube_planewave_problem(n=args.n, degree=args.degree, seed=args.seed, n_sources=args.nrhs)
-        wl = f"unit cube {args.n}^3 Kuhn, r={args.degree}, plane wave, 2x2x2 boxes"
-    lay = Layout.from_problem(prob)
-    info = lay.info()
-    t_mesh = time.perf_counter() - t0
-    log(f"[bench] {wl}: ndof={info.ndof} nnz={info.nnz} n_sub={info.n_sub} max_ns={info.max_ns} "
-        f"sum_ns2={info.sum_ns2:.3e} host setup {t_mesh:.1f}s")
+    prob, lay, info, wl, t_mesh = build_workload(args)
     footprint = lay.footprint(precision, args.nrhs)
     log(f"[bench] device footprint {footprint/1e9:.1f} GB")
 
@@ -310,48 +400,14 @@ def main():
     elapsed = time.perf_counter() - t_start
     timing(False)
 
-    ktimes = {}
-    for name in ("lu", "local_solve", "local_solve_multi", "spmv", "assemble", "local_assemble"):
-        ms, n = kernel_time(name)
-        ktimes[name] = (ms, n)
-    rsz = 8 if precision == B.MXW_FP64 else 4
-    lu_flops = 8.0 / 3.0 * info.sum_ns3            # complex LU: 8 n^3 / 3 real flops
-    solve_bytes = 2 * rsz * info.sum_ns2 + 16 * info.sum_ns * 2 + 16 * info.ndof * 2
-    kern = {}
-    if ktimes["lu"][1]:
-        avg = ktimes["lu"][0] / ktimes["lu"][1] / 1e3
-        peak = FP64_PEAK_TFLOPS if precision == B.MXW_FP64 else FP32_PEAK_TFLOPS
-        kern["lu"] = dict(bound="mfma", achieved=lu_flops / avg / 1e12, peak=peak, unit="TFLOP/s",
-                          avg_ms=avg * 1e3, launches=ktimes["lu"][1], total_ms=ktimes["lu"][0])
-    if ktimes["local_solve"][1]:
-        avg = ktimes["local_solve"][0] / ktimes["local_solve"][1] / 1e3
-        kern["local_solve"] = dict(bound="hbm", achieved=args.nrhs * solve_bytes / avg / 1e9, peak=HBM_PEAK_GBS,
-                                   unit="GB/s", avg_ms=avg * 1e3, launches=ktimes["local_solve"][1],
-                                   total_ms=ktimes["local_solve"][0])
-    if ktimes["local_solve_multi"][1]:
-        # all columns of a chunk per factor read: MFMA-bound at 32 columns
-        avg = ktimes["local_solve_multi"][0] / ktimes["local_solve_multi"][1] / 1e3
-        flops = 8.0 * info.sum_ns2 * args.nrhs
-        peak = FP64_PEAK_TFLOPS if precision == B.MXW_FP64 else FP32_PEAK_TFLOPS
-        kern["local_solve_multi"] = dict(bound="mfma", achieved=flops / avg / 1e12, peak=peak, unit="TFLOP/s",
-                                         avg_ms=avg * 1e3, launches=ktimes["local_solve_multi"][1],
-                                         total_ms=ktimes["local_solve_multi"][0],
-                                         factor_GBps=2 * rsz * info.sum_ns2 / avg / 1e9)
-    if ktimes["spmv"][1]:
-        avg = ktimes["spmv"][0] / ktimes["spmv"][1] / 1e3
-        spmv_bytes = 20 * info.nnz + 8 * (info.ndof + 1) + 32 * info.ndof * args.nrhs
-        kern["spmv"] = dict(bound="hbm", achieved=spmv_bytes / avg / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-                            avg_ms=avg * 1e3, launches=ktimes["spmv"][1], total_ms=ktimes["spmv"][0])
+    kern = kernel_rooflines(info, precision, args.nrhs)
     dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else None
     roof = None
     if dom:
         kd = kern[dom]
         roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
                 "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"],
-                "traffic": measured_traffic(dom, args.workload, args.precision)}
-    for k, v in kern.items():
-        v["frac"] = v["achieved"] / v["peak"]
-
+                "traffic": measured_traffic(dom, args.precision, args.nrhs)}
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.nrhs * args.steps / elapsed
     out = {

@@ -8,14 +8,116 @@
 // row of X is contiguous) lives in a global scratch buffer.  Forward sweep over
 // 32-row blocks b:  T_b = X_b - L_{b,<b} X_{<b}  (MFMA, K = rows before b),
 // X_b = L_bb^{-1} T_b (the diagonal block holds L_bb^{-1}); backward likewise
-// with U and U_bb^{-1}.  The K range of each product is split over the four
-// waves, whose 32 x 32 partial products are summed in LDS.
+// with U and U_bb^{-1}.  Rows are taken 64 at a time (two diagonal blocks) so
+// that X is re-read once per 64 rows; the waves split the 64 rows in halves
+// and the K range in two, and the two partial products are summed in LDS.
 #include "device.h"
 #include "kernels.h"
 
 namespace mxw {
 
 constexpr int kMultiPC = 32;   // columns per chunk
+
+// Y = M T on MFMA for 32 x 32 M and T in LDS; each wave forms a 16 x 16
+// tile (rows (wave & 1) * 16.., columns (wave >> 1) * 16..).  mode selects M
+// from the staged block B: 0: B itself; 1: unit lower, I + strict part of B;
+// 2: upper part of B.  Rows and columns of M at or beyond bn are zero.
+template <typename R, int NB, int PC>
+__device__ __forceinline__ void tile_product(const R (*Br)[NB + 1], const R (*Bi)[NB + 1], int mode, int bn,
+                                             const R (*Tr)[PC + 1], const R (*Ti)[PC + 1],
+                                             typename Mfma<R>::acc_t& yre, typename Mfma<R>::acc_t& yim) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r = (wave & 1) * 16 + li, c = (wave >> 1) * 16 + li;
+#pragma unroll
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    const int q = k0 + lk;
+    R mr = R(0), mi = R(0);
+    if (r < bn && q < bn) {
+      if (mode == 0 || (mode == 1 && q < r) || (mode == 2 && q >= r)) {
+        mr = Br[r][q];
+        mi = Bi[r][q];
+      } else if (mode == 1 && q == r) {
+        mr = R(1);
+      }
+    }
+    const R tr = Tr[q][c], ti = Ti[q][c];
+    yre = Mfma<R>::op(mr, tr, yre);
+    yre = Mfma<R>::op(-mi, ti, yre);
+    yim = Mfma<R>::op(mr, ti, yim);
+    yim = Mfma<R>::op(mi, tr, yim);
+  }
+}
+
+// Buffer loads: a descriptor per plane bounds every access (an offset at or
+// past the end of the plane reads 0).  Masked entries take the offset kOob,
+// beyond every plane (a plane is at most 8192 x 8200 x 8 B < 1 GiB), so they
+// read 0 without a branch around the load.
+constexpr int kBufferFlags = 0x00020000;   // raw 32-bit buffer, gfx9 family
+constexpr int kOob = 0x40000000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kBufferFlags);
+}
+
+template <typename R>
+struct BufLoad;
+template <>
+struct BufLoad<float> {
+  __device__ __forceinline__ static float at(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+  }
+};
+template <>
+struct BufLoad<double> {
+  __device__ __forceinline__ static double at(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+  }
+};
+
+// One K slice of the super-block product: 4*KU consecutive k (factor columns
+// / rows of X), masked to zero past k_hi and past the super-block's rows,
+// then accumulated on MFMA.
+template <typename R, int KU, int PC>
+struct Slice {
+  R ar[2][KU], ai[2][KU], xr[2][KU], xi[2][KU];
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t fr, __amdgpu_buffer_rsrc_t fi,
+                                       __amdgpu_buffer_rsrc_t xrr, __amdgpu_buffer_rsrc_t xir, int ld, int arow,
+                                       const bool (&row_ok)[2], int k0, int k_hi, int lk, int li) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int kk = k0 + 4 * u + lk;
+      const bool ok = kk < k_hi;
+      const int fo = (kk * ld + arow) * (int)sizeof(R);
+      const int xo = ok ? (kk * PC + li) * (int)sizeof(R) : kOob;
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const int o = (ok && row_ok[rt]) ? fo + rt * 16 * (int)sizeof(R) : kOob;
+        ar[rt][u] = BufLoad<R>::at(fr, o);
+        ai[rt][u] = BufLoad<R>::at(fi, o);
+      }
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        xr[ct][u] = BufLoad<R>::at(xrr, xo + ct * 16 * (int)sizeof(R));
+        xi[ct][u] = BufLoad<R>::at(xir, xo + ct * 16 * (int)sizeof(R));
+      }
+    }
+  }
+  template <typename Acc>
+  __device__ __forceinline__ void product(Acc (&pre)[2][2], Acc (&pim)[2][2]) const {
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          pre[rt][ct] = Mfma<R>::op(ar[rt][u], xr[ct][u], pre[rt][ct]);
+          pre[rt][ct] = Mfma<R>::op(-ai[rt][u], xi[ct][u], pre[rt][ct]);
+          pim[rt][ct] = Mfma<R>::op(ar[rt][u], xi[ct][u], pim[rt][ct]);
+          pim[rt][ct] = Mfma<R>::op(ai[rt][u], xr[ct][u], pim[rt][ct]);
+        }
+  }
+};
 
 template <typename R, int NB, int PC>
 __global__ void __launch_bounds__(256) k_local_solve_multi(
@@ -25,10 +127,12 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
     double2* __restrict__ z, int64_t zstride, R* __restrict__ xbuf, int64_t xchunk, int ncol,
     const int* __restrict__ active, const int* __restrict__ order) {
   static_assert(NB == 32 && PC == 32, "tile shape assumes 32 x 32 blocks");
+  constexpr int SB = 2 * NB;   // rows per pass over the factor
+  constexpr int KU = 8;        // 4-wide k steps per K slice
   typedef typename Mfma<R>::acc_t acc_t;
-  // Sr/Si[2]: partial products of the waves, then T_b in slot 0
-  __shared__ R Sr[2][NB][PC + 1], Si[2][NB][PC + 1];
-  __shared__ R Dr[NB][NB + 1], Di[NB][NB + 1];     // diagonal inverse block [row][col]
+  __shared__ R Tr[SB][PC + 1], Ti[SB][PC + 1];       // T of the super-block
+  __shared__ R Br[3][NB][NB + 1], Bi[3][NB][NB + 1];  // diagonal block solved first, coupling block, second diagonal block
+  __shared__ R Yr[NB][PC + 1], Yi[NB][PC + 1];       // solution of the block solved first
   const int s = order ? order[blockIdx.x] : blockIdx.x;
   const int chunk = blockIdx.y, c0 = chunk * PC;
   const int n = nsz[s];
@@ -41,26 +145,70 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
   R* Xi = Xr + (int64_t)n * PC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int rh = wave & 1, kh = wave >> 1;   // row half of the super-block, half of the K slices
+  const __amdgpu_buffer_rsrc_t fr = plane_rsrc(Ar, ld * n * (int64_t)sizeof(R));
+  const __amdgpu_buffer_rsrc_t fi = plane_rsrc(Ai, ld * n * (int64_t)sizeof(R));
+  const __amdgpu_buffer_rsrc_t xrr = plane_rsrc(Xr, (int64_t)n * PC * sizeof(R));
+  const __amdgpu_buffer_rsrc_t xir = plane_rsrc(Xi, (int64_t)n * PC * sizeof(R));
 
-  for (int idx = tid; idx < n * PC; idx += 256) {
-    const int i = idx / PC, c = idx % PC, col = c0 + c;
-    double2 a = make_double2(0.0, 0.0);
-    if (col < ncol) a = v[(int64_t)col * vstride + D[P[i]]];
-    Xr[idx] = (R)a.x;
-    Xi[idx] = (R)a.y;
+  // restrict and permute: X = P_s R_s v (4 entries in flight per thread)
+  for (int base = tid; base < n * PC; base += 4 * 256) {
+    double2 a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * 256;
+      a[u] = make_double2(0.0, 0.0);
+      if (idx < n * PC) {
+        const int i = idx / PC, col = c0 + idx % PC;
+        if (col < ncol) a[u] = v[(int64_t)col * vstride + D[P[i]]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * 256;
+      if (idx < n * PC) {
+        Xr[idx] = (R)a[u].x;
+        Xi[idx] = (R)a[u].y;
+      }
+    }
   }
   __syncthreads();
 
+  const int nsb = (n + SB - 1) / SB;
   for (int sweep = 0; sweep < 2; ++sweep) {
-    const int nblk = (n + NB - 1) / NB;
-    for (int bq = 0; bq < nblk; ++bq) {
-      const int b = sweep == 0 ? bq : nblk - 1 - bq;
-      const int b0 = b * NB, bn = min(NB, n - b0);
-      // K range: [0, b0) forward, [b0 + bn, n) backward, split over the
-      // waves in 32-wide slices (slice q goes to wave q mod 4); every wave
-      // forms the whole 32 x 32 partial product of its slices, so each
-      // factor entry and each entry of X is loaded once per workgroup
-      const int k_lo = sweep == 0 ? 0 : b0 + bn, k_hi = sweep == 0 ? b0 : n;
+    for (int sq = 0; sq < nsb; ++sq) {
+      const int sb = sweep == 0 ? sq : nsb - 1 - sq;
+      const int r0 = sb * SB, rn = min(SB, n - r0);
+      // 32-row blocks in solve order: forward 0 then 1, backward 1 then 0
+      const int bf = sweep == 0 ? 0 : 1, bs = 1 - bf;
+      const int nf = max(0, min(NB, rn - bf * NB)), ns = max(0, min(NB, rn - bs * NB));
+      // prefetch, before the long product: the three factor blocks of the
+      // triangular part and X of the super-block
+      R pbr[3][4], pbi[3][4], pxr[8], pxi[8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+        const int rows[3] = {bf, bs, bs}, cols[3] = {bf, bf, bs};
+        const int rlim[3] = {nf, ns, ns}, clim[3] = {nf, nf, ns};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const bool in = r < rlim[m] && c < clim[m];
+          const int o = in ? ((r0 + cols[m] * NB + c) * (int)ld + r0 + rows[m] * NB + r) * (int)sizeof(R) : kOob;
+          pbr[m][j] = BufLoad<R>::at(fr, o);
+          pbi[m][j] = BufLoad<R>::at(fi, o);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int idx = tid + 256 * j;
+        const int o = idx / PC < rn ? (r0 * PC + idx) * (int)sizeof(R) : kOob;
+        pxr[j] = BufLoad<R>::at(xrr, o);
+        pxi[j] = BufLoad<R>::at(xir, o);
+      }
+      // (L or U)[sb rows, K] X_K over K = [0, r0) forward, [r0 + rn, n)
+      // backward: waves (rh, kh) form rows rh*32.. of the product over the
+      // 32-wide K slices q with q mod 2 == kh
+      const int k_lo = sweep == 0 ? 0 : r0 + rn, k_hi = sweep == 0 ? r0 : n;
       acc_t pre[2][2], pim[2][2];
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
@@ -71,104 +219,87 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
         }
       bool row_ok[2];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) row_ok[rt] = rt * 16 + li < bn;
-      for (int k0 = k_lo + 32 * wave; k0 < k_hi; k0 += 128) {
-        R ar[2][8], ai[2][8], xr[2][8], xi[2][8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int kk = k0 + 4 * u + lk;
-          const bool ok = kk < k_hi;
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt) {
-            const int64_t o = (int64_t)kk * ld + b0 + rt * 16 + li;
-            ar[rt][u] = (ok && row_ok[rt]) ? Ar[o] : R(0);
-            ai[rt][u] = (ok && row_ok[rt]) ? Ai[o] : R(0);
-          }
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            const int64_t o = (int64_t)kk * PC + ct * 16 + li;
-            xr[ct][u] = ok ? Xr[o] : R(0);
-            xi[ct][u] = ok ? Xi[o] : R(0);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-              pre[rt][ct] = Mfma<R>::op(ar[rt][u], xr[ct][u], pre[rt][ct]);
-              pre[rt][ct] = Mfma<R>::op(-ai[rt][u], xi[ct][u], pre[rt][ct]);
-              pim[rt][ct] = Mfma<R>::op(ar[rt][u], xi[ct][u], pim[rt][ct]);
-              pim[rt][ct] = Mfma<R>::op(ai[rt][u], xr[ct][u], pim[rt][ct]);
-            }
+      for (int rt = 0; rt < 2; ++rt) row_ok[rt] = rh * NB + rt * 16 + li < rn;
+      const int arow = r0 + rh * NB + li;
+      for (int k0 = k_lo + 4 * KU * kh; k0 < k_hi; k0 += 8 * KU) {
+        Slice<R, KU, PC> sl;
+        sl.load(fr, fi, xrr, xir, (int)ld, arow, row_ok, k0, k_hi, lk, li);
+        sl.product(pre, pim);
       }
-      // sum the four partial products: waves 0,1 store, waves 2,3 add
-      for (int phase = 0; phase < 2; ++phase) {
-        if ((wave >> 1) == phase) {
-          const int slot = wave & 1;
+      // T = X_sb - product (kh = 1 subtracts first, then kh = 0); stage blocks
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
+        Tr[r][c] = pxr[j];
+        Ti[r][c] = pxi[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          Br[m][r][c] = pbr[m][j];
+          Bi[m][r][c] = pbi[m][j];
+        }
+      }
+      __syncthreads();
+      for (int phase = 1; phase >= 0; --phase) {
+        if (kh == phase) {
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
-                const int r = rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
-                if (phase == 0) {
-                  Sr[slot][r][c] = pre[rt][ct][q];
-                  Si[slot][r][c] = pim[rt][ct][q];
-                } else {
-                  Sr[slot][r][c] += pre[rt][ct][q];
-                  Si[slot][r][c] += pim[rt][ct][q];
-                }
+                const int r = rh * NB + rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
+                Tr[r][c] -= pre[rt][ct][q];
+                Ti[r][c] -= pim[rt][ct][q];
               }
         }
         __syncthreads();
       }
-      // T_b = X_b - (L or U) X in slot 0; stage the inverse diagonal block
-      for (int idx = tid; idx < NB * PC; idx += 256) {
-        const int r = idx / PC, c = idx % PC;
-        R tr = R(0), ti = R(0);
-        if (r < bn) {
-          tr = Xr[(int64_t)(b0 + r) * PC + c] - (Sr[0][r][c] + Sr[1][r][c]);
-          ti = Xi[(int64_t)(b0 + r) * PC + c] - (Si[0][r][c] + Si[1][r][c]);
-        }
-        Sr[0][r][c] = tr;
-        Si[0][r][c] = ti;
-      }
-      for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int r = idx % NB, c = idx / NB;
-        R vr = R(0), vi = R(0);
-        if (r < bn && c < bn) {
-          vr = Ar[(int64_t)(b0 + c) * ld + b0 + r];
-          vi = Ai[(int64_t)(b0 + c) * ld + b0 + r];
-        }
-        Dr[r][c] = vr;
-        Di[r][c] = vi;
-      }
-      __syncthreads();
-      // X_b = L_bb^{-1} T_b (unit lower, strict part stored) or U_bb^{-1} T_b
-      for (int idx = tid; idx < NB * PC; idx += 256) {
-        const int r = idx / PC, c = idx % PC;
-        if (r >= bn) continue;
-        R yr, yi;
-        if (sweep == 0) {
-          yr = Sr[0][r][c];
-          yi = Si[0][r][c];
-          for (int q = 0; q < r; ++q) {
-            yr += Dr[r][q] * Sr[0][q][c] - Di[r][q] * Si[0][q][c];
-            yi += Dr[r][q] * Si[0][q][c] + Di[r][q] * Sr[0][q][c];
-          }
-        } else {
-          yr = R(0);
-          yi = R(0);
-          for (int q = r; q < bn; ++q) {
-            yr += Dr[r][q] * Sr[0][q][c] - Di[r][q] * Si[0][q][c];
-            yi += Dr[r][q] * Si[0][q][c] + Di[r][q] * Sr[0][q][c];
+      // triangular part: Y = M_f T_f; T_s -= C Y; X_s = M_s T_s, with M the
+      // diagonal inverse (unit lower forward, upper backward) and C the
+      // coupling block (rows of the second block, columns of the first)
+      const int mode = sweep == 0 ? 1 : 2;
+      const int orow = (wave & 1) * 16, ocol = (wave >> 1) * 16 + li;
+      if (nf > 0) {
+        acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+        tile_product<R, NB, PC>(Br[0], Bi[0], mode, nf, Tr + bf * NB, Ti + bf * NB, yre, yim);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = orow + Mfma<R>::row(lane, q);
+          Yr[r][ocol] = yre[q];
+          Yi[r][ocol] = yim[q];
+          if (r < nf) {
+            Xr[(int64_t)(r0 + bf * NB + r) * PC + ocol] = yre[q];
+            Xi[(int64_t)(r0 + bf * NB + r) * PC + ocol] = yim[q];
           }
         }
-        Xr[(int64_t)(b0 + r) * PC + c] = yr;
-        Xi[(int64_t)(b0 + r) * PC + c] = yi;
+        __syncthreads();
+        if (ns > 0) {
+          acc_t cre = acc_t{0, 0, 0, 0}, cim = acc_t{0, 0, 0, 0};
+          tile_product<R, NB, PC>(Br[1], Bi[1], 0, NB, Yr, Yi, cre, cim);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = orow + Mfma<R>::row(lane, q);
+            Tr[bs * NB + r][ocol] -= cre[q];
+            Ti[bs * NB + r][ocol] -= cim[q];
+          }
+          __syncthreads();
+        }
+      }
+      if (ns > 0) {
+        acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+        tile_product<R, NB, PC>(Br[2], Bi[2], mode, ns, Tr + bs * NB, Ti + bs * NB, yre, yim);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = orow + Mfma<R>::row(lane, q);
+          if (r < ns) {
+            Xr[(int64_t)(r0 + bs * NB + r) * PC + ocol] = yre[q];
+            Xi[(int64_t)(r0 + bs * NB + r) * PC + ocol] = yim[q];
+          }
+        }
       }
       __syncthreads();
     }
