@@ -19,28 +19,17 @@ namespace mxw {
 constexpr int kMultiPC = 32;   // columns per chunk
 
 // Y = M T on MFMA for 32 x 32 M and T in LDS; each wave forms a 16 x 16
-// tile (rows (wave & 1) * 16.., columns (wave >> 1) * 16..).  mode selects M
-// from the staged block B: 0: B itself; 1: unit lower, I + strict part of B;
-// 2: upper part of B.  Rows and columns of M at or beyond bn are zero.
+// tile (rows (wave & 1) * 16.., columns (wave >> 1) * 16..).
 template <typename R, int NB, int PC>
-__device__ __forceinline__ void tile_product(const R (*Br)[NB + 1], const R (*Bi)[NB + 1], int mode, int bn,
-                                             const R (*Tr)[PC + 1], const R (*Ti)[PC + 1],
+__device__ __forceinline__ void tile_product(const R (*Br)[NB + 1], const R (*Bi)[NB + 1],
+                                             const R (*Tr)[PC + 1], const R (*Ti)[PC + 1], int lane, int wave,
                                              typename Mfma<R>::acc_t& yre, typename Mfma<R>::acc_t& yim) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int r = (wave & 1) * 16 + li, c = (wave >> 1) * 16 + li;
 #pragma unroll
   for (int k0 = 0; k0 < NB; k0 += 4) {
     const int q = k0 + lk;
-    R mr = R(0), mi = R(0);
-    if (r < bn && q < bn) {
-      if (mode == 0 || (mode == 1 && q < r) || (mode == 2 && q >= r)) {
-        mr = Br[r][q];
-        mi = Bi[r][q];
-      } else if (mode == 1 && q == r) {
-        mr = R(1);
-      }
-    }
+    const R mr = Br[r][q], mi = Bi[r][q];
     const R tr = Tr[q][c], ti = Ti[q][c];
     yre = Mfma<R>::op(mr, tr, yre);
     yre = Mfma<R>::op(-mi, ti, yre);
@@ -177,14 +166,19 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
   const int nsb = (n + SB - 1) / SB;
   for (int sweep = 0; sweep < 2; ++sweep) {
     for (int sq = 0; sq < nsb; ++sq) {
+      // lane-derived indices recomputed per pass (an opaque copy of the
+      // thread id) instead of being held in registers across the whole kernel
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      const int lane = tid & 63, li = lane & 15, lk = lane >> 4;
       const int sb = sweep == 0 ? sq : nsb - 1 - sq;
       const int r0 = sb * SB, rn = min(SB, n - r0);
       // 32-row blocks in solve order: forward 0 then 1, backward 1 then 0
       const int bf = sweep == 0 ? 0 : 1, bs = 1 - bf;
       const int nf = max(0, min(NB, rn - bf * NB)), ns = max(0, min(NB, rn - bs * NB));
       // prefetch, before the long product: the three factor blocks of the
-      // triangular part and X of the super-block
-      R pbr[3][4], pbi[3][4], pxr[8], pxi[8];
+      // triangular part
+      R pbr[3][4], pbi[3][4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
@@ -197,13 +191,6 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
           pbr[m][j] = BufLoad<R>::at(fr, o);
           pbi[m][j] = BufLoad<R>::at(fi, o);
         }
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int idx = tid + 256 * j;
-        const int o = idx / PC < rn ? (r0 * PC + idx) * (int)sizeof(R) : kOob;
-        pxr[j] = BufLoad<R>::at(xrr, o);
-        pxi[j] = BufLoad<R>::at(xir, o);
       }
       // (L or U)[sb rows, K] X_K over K = [0, r0) forward, [r0 + rn, n)
       // backward: waves (rh, kh) form rows rh*32.. of the product over the
@@ -221,25 +208,38 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) row_ok[rt] = rh * NB + rt * 16 + li < rn;
       const int arow = r0 + rh * NB + li;
+      // every load of a slice is issued ahead of its products (scheduling
+      // barrier), so the 64 loads of a wave are in flight together
       for (int k0 = k_lo + 4 * KU * kh; k0 < k_hi; k0 += 8 * KU) {
         Slice<R, KU, PC> sl;
         sl.load(fr, fi, xrr, xir, (int)ld, arow, row_ok, k0, k_hi, lk, li);
+        __builtin_amdgcn_sched_barrier(0);
         sl.product(pre, pim);
       }
       // T = X_sb - product (kh = 1 subtracts first, then kh = 0); stage blocks
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
-        Tr[r][c] = pxr[j];
-        Ti[r][c] = pxi[j];
+        const int o = r < rn ? (r0 * PC + idx) * (int)sizeof(R) : kOob;
+        Tr[r][c] = BufLoad<R>::at(xrr, o);
+        Ti[r][c] = BufLoad<R>::at(xir, o);
       }
+      // the diagonal inverses as full matrices: unit lower (I + strict part)
+      // forward, upper part backward; zero outside the block
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-          Br[m][r][c] = pbr[m][j];
-          Bi[m][r][c] = pbi[m][j];
+          R vr = pbr[m][j], vi = pbi[m][j];
+          if (m != 1) {
+            const int bn = m == 0 ? nf : ns;
+            const bool keep = sweep == 0 ? c < r : c >= r;
+            vr = keep ? vr : (sweep == 0 && c == r && r < bn ? R(1) : R(0));
+            vi = keep ? vi : R(0);
+          }
+          Br[m][r][c] = vr;
+          Bi[m][r][c] = vi;
         }
       }
       __syncthreads();
@@ -261,11 +261,10 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
       // triangular part: Y = M_f T_f; T_s -= C Y; X_s = M_s T_s, with M the
       // diagonal inverse (unit lower forward, upper backward) and C the
       // coupling block (rows of the second block, columns of the first)
-      const int mode = sweep == 0 ? 1 : 2;
       const int orow = (wave & 1) * 16, ocol = (wave >> 1) * 16 + li;
       if (nf > 0) {
         acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
-        tile_product<R, NB, PC>(Br[0], Bi[0], mode, nf, Tr + bf * NB, Ti + bf * NB, yre, yim);
+        tile_product<R, NB, PC>(Br[0], Bi[0], Tr + bf * NB, Ti + bf * NB, lane, wave, yre, yim);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = orow + Mfma<R>::row(lane, q);
@@ -279,7 +278,7 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
         __syncthreads();
         if (ns > 0) {
           acc_t cre = acc_t{0, 0, 0, 0}, cim = acc_t{0, 0, 0, 0};
-          tile_product<R, NB, PC>(Br[1], Bi[1], 0, NB, Yr, Yi, cre, cim);
+          tile_product<R, NB, PC>(Br[1], Bi[1], Yr, Yi, lane, wave, cre, cim);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int r = orow + Mfma<R>::row(lane, q);
@@ -291,7 +290,7 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
       }
       if (ns > 0) {
         acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
-        tile_product<R, NB, PC>(Br[2], Bi[2], mode, ns, Tr + bs * NB, Ti + bs * NB, yre, yim);
+        tile_product<R, NB, PC>(Br[2], Bi[2], Tr + bs * NB, Ti + bs * NB, lane, wave, yre, yim);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = orow + Mfma<R>::row(lane, q);
