@@ -324,6 +324,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--krylov", default="pseudo", choices=["pseudo", "block"],
+                    help="pseudo-block (one Krylov space per source) or block GMRES (one shared space)")
     ap.add_argument("--graph", action="store_true",
                     help="replay each Arnoldi step as a captured HIP graph (kernel timers are off inside graphs)")
     args = ap.parse_args()
@@ -369,7 +371,8 @@ def main():
         P = holder["P"]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, it, rr, st = P.solve(prob.sources[:args.nrhs], use_graph=int(args.graph))
+        krylov = B.MXW_KRYLOV_BLOCK if args.krylov == "block" else B.MXW_KRYLOV_PSEUDOBLOCK
+        x, it, rr, st = P.solve(prob.sources[:args.nrhs], use_graph=int(args.graph), krylov=krylov)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         phases.append((t1 - t0, t2 - t1))
@@ -416,7 +419,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if precision == B.MXW_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": wl, "ndof": int(info.ndof), "nnz": int(info.nnz), "n_sub": int(info.n_sub),
                    "max_ns": int(info.max_ns), "nrhs": args.nrhs, "precision": args.precision,
-                   "iterations": iters, "restart": 50, "tol": 1e-8, "graph": bool(args.graph)},
+                   "iterations": iters, "restart": 50, "tol": 1e-8, "graph": bool(args.graph),
+                   "krylov": args.krylov},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "mesh_setup_s": t_mesh,
         "phase_s": {"assemble_factor": float(np.median([p[0] for p in phases[-args.steps:]])),

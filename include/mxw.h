@@ -67,6 +67,12 @@ enum { MXW_BC_PEC = 0, MXW_BC_IMPEDANCE = 1 };
  * with everything else (assembly, SpMV, Arnoldi, least squares) in FP64 */
 enum { MXW_FP64 = 0, MXW_MIXED = 1 };
 enum { MXW_SRC_DIPOLE = 0, MXW_SRC_PLANEWAVE = 1 };
+/* multi-source Krylov drivers (Sec. 5): PSEUDOBLOCK = one Krylov space per
+ * right-hand side, all operations fused over the columns; BLOCK = one shared
+ * block Krylov space (block CGS2 orthogonalisation, Cholesky QR of each new
+ * block, Householder block least squares), at most 32 independent, non-zero
+ * right-hand sides per solve (MXW_EINVAL otherwise); a block that loses rank
+ * before convergence ends the solve with MXW_EBREAKDOWN. */
 enum { MXW_KRYLOV_PSEUDOBLOCK = 0, MXW_KRYLOV_BLOCK = 1 };
 /* preconditioner variants (Sec. 4): ORAS (default), OAS (no D_s),
  * RAS (Dirichlet transmission: A_s = R_s A R_s^T, with D_s) */
@@ -204,10 +210,12 @@ mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_
 mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double* v_dev, double* z_dev,
                                   void* stream);
 
-/* Solves A x_j = b_j for nrhs sources with FGMRES + ORAS.  E_out: complex128
- * [nrhs][ndof] on the device (E_out_is_device = 1) or host.  iters_out
- * [nrhs] and relres_out [nrhs] (true relative residuals) may be NULL.
- * Returns MXW_ENOTCONV if any column missed tol within max_iters. */
+/* Solves A x_j = b_j for nrhs sources with FGMRES + ORAS (right
+ * preconditioning, x0 = 0; pseudo-block or block per opts->krylov).  E_out:
+ * complex128 [nrhs][ndof] on the device (E_out_is_device = 1) or host.
+ * iters_out [nrhs] (Arnoldi steps; block steps in block mode) and relres_out
+ * [nrhs] (true relative residuals) may be NULL.  Returns MXW_ENOTCONV if any
+ * column missed tol within max_iters. */
 mxw_status mxw_solve(mxw_problem* prob, int32_t nrhs, const mxw_source* src,
                      const mxw_solve_opts* opts, void* stream, double* E_out,
                      int32_t E_out_is_device, int32_t* iters_out, double* relres_out);

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmxw.so")
-SOURCES = ["basis.cpp", "layout.cpp", "fem_kernels.hip", "lu_kernels.hip", "solve_kernels.hip", "multi_solve.hip", "api.hip"]
+SOURCES = ["basis.cpp", "layout.cpp", "fem_kernels.hip", "lu_kernels.hip", "solve_kernels.hip", "multi_solve.hip", "block_krylov.hip", "api.hip"]
 
 
 def hipcc_cmd(out: str, extra=()):
@@ -19,6 +19,8 @@ def hipcc_cmd(out: str, extra=()):
            "-Wno-unused-result", "-o", out]
     cmd += list(extra)
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
+    # rocBLAS: the plain complex GEMMs of block GMRES (tall basis products)
+    cmd += ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     return cmd
 
 

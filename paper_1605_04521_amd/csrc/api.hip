@@ -1,6 +1,7 @@
 // C ABI of the library: layouts, device problems, ORAS application and the
 // FGMRES driver (Sec. 4-5 of the paper).
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -231,6 +232,25 @@ struct KrylovWork {
   std::vector<std::vector<double>> history;   // per column: |g_{j+1}| / ||b|| of every step
 };
 
+// Block GMRES workspace (one shared Krylov space for p right-hand sides); the
+// bases V, Z and the vectors W, R of KrylovWork are reused with block layout
+// (vector i*p + c of the basis is column c of block i).
+struct BlockWork {
+  int p = 0, m = 0, nparts = 0;
+  int64_t ndof = 0, kc = 0;
+  DevMem mem;
+  double2 *H1 = nullptr, *H2 = nullptr, *Hc = nullptr, *part = nullptr, *G = nullptr, *G0 = nullptr, *R1 = nullptr,
+          *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *S = nullptr, *T = nullptr, *Rls = nullptr, *E = nullptr,
+          *Y = nullptr;
+  double* est = nullptr;
+  int* info = nullptr;   // [0] rank loss, [1] second Gram-Schmidt pass needed
+  int64_t reorth = 0;    // second passes in the last solve
+  rocblas_handle h = nullptr;
+  ~BlockWork() {
+    if (h) rocblas_destroy_handle(h);
+  }
+};
+
 struct mxw_problem {
   explicit mxw_problem(std::shared_ptr<LayoutShared> s) : S(std::move(s)), L(S->L) {}
   std::shared_ptr<LayoutShared> S;
@@ -272,6 +292,7 @@ struct mxw_problem {
   bool mixed = false;
   int spmv_group = 16;
   KrylovWork kw;
+  BlockWork bw;
 };
 
 namespace {
@@ -899,6 +920,212 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
   return result;
 }
 
+
+// ---------------------------------------------------------------------------
+// block FGMRES (one Krylov space shared by the p right-hand sides)
+// ---------------------------------------------------------------------------
+#define BLAS_CHECK(x)                                                         \
+  do {                                                                        \
+    rocblas_status s_ = (x);                                                  \
+    if (s_ != rocblas_status_success) {                                       \
+      set_error(std::string(#x) + ": " + rocblas_status_to_string(s_));       \
+      return MXW_EDEVICE;                                                     \
+    }                                                                         \
+  } while (0)
+
+typedef rocblas_double_complex zc;
+
+mxw_status ensure_block(mxw_problem* P, int p, int m) {
+  BlockWork& b = P->bw;
+  const int64_t n = P->L.ndof;
+  if (b.p == p && b.m == m && b.ndof == n && b.H1) return MXW_OK;
+  b.mem.reset();
+  b.p = p;
+  b.m = m;
+  b.ndof = n;
+  // split-K chunk of the Gram products: about 64 partial products
+  b.kc = std::max<int64_t>(2048, ((n + 63) / 64 + 255) / 256 * 256);
+  b.nparts = (int)((n + b.kc - 1) / b.kc);
+  const int64_t Q = (int64_t)(m + 1) * p;
+  b.H1 = b.mem.alloc<double2>(Q * p);
+  b.H2 = b.mem.alloc<double2>(Q * p);
+  b.Hc = b.mem.alloc<double2>(Q * p);
+  b.part = b.mem.alloc<double2>((size_t)b.nparts * Q * p);
+  b.G = b.mem.alloc<double2>(p * p);
+  b.G0 = b.mem.alloc<double2>(p * p);
+  b.R1 = b.mem.alloc<double2>(p * p);
+  b.R1i = b.mem.alloc<double2>(p * p);
+  b.R2 = b.mem.alloc<double2>(p * p);
+  b.R2i = b.mem.alloc<double2>(p * p);
+  b.S = b.mem.alloc<double2>(p * p);
+  b.T = b.mem.alloc<double2>((size_t)m * 4 * p * p);
+  b.Rls = b.mem.alloc<double2>((size_t)m * p * m * p);
+  b.E = b.mem.alloc<double2>(Q * p);
+  b.Y = b.mem.alloc<double2>((size_t)m * p * p);
+  b.est = b.mem.alloc<double>(p);
+  b.info = b.mem.alloc<int>(2);
+  if (!b.H1 || !b.H2 || !b.Hc || !b.part || !b.G || !b.G0 || !b.R1 || !b.R1i || !b.R2 || !b.R2i || !b.S || !b.T || !b.Rls ||
+      !b.E || !b.Y || !b.est || !b.info) {
+    b.H1 = nullptr;
+    set_error("block Krylov workspace allocation failed");
+    return MXW_ENOMEM;
+  }
+  if (!b.h) BLAS_CHECK(rocblas_create_handle(&b.h));
+  return MXW_OK;
+}
+
+// out (Q x p, column-major) = A^H W, A: Q vectors of length n, W: p vectors,
+// as split-K partial products (rocBLAS) summed in a fixed order
+mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const double2* W, int p, double2* out) {
+  BlockWork& b = P->bw;
+  const int64_t n = P->L.ndof, kc = b.kc, nfull = n / kc, tail = n - nfull * kc;
+  const zc one(1.0, 0.0), zero(0.0, 0.0);
+  BLAS_CHECK(rocblas_set_stream(b.h, st));
+  if (nfull > 0)
+    BLAS_CHECK(rocblas_zgemm_strided_batched(b.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, Q, p,
+                                             (rocblas_int)kc, &one, (const zc*)A, (rocblas_int)n, kc, (const zc*)W,
+                                             (rocblas_int)n, kc, &zero, (zc*)b.part, Q, (int64_t)Q * p,
+                                             (rocblas_int)nfull));
+  if (tail > 0)
+    BLAS_CHECK(rocblas_zgemm(b.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, Q, p,
+                             (rocblas_int)tail, &one, (const zc*)(A + nfull * kc), (rocblas_int)n,
+                             (const zc*)(W + nfull * kc), (rocblas_int)n, &zero,
+                             (zc*)(b.part + nfull * (int64_t)Q * p), Q));
+  launch_gram_reduce(st, (int64_t)Q * p, (int)(nfull + (tail > 0)), b.part, out);
+  return MXW_OK;
+}
+
+// C (n x p) = alpha A M + beta C; A: K vectors of length n, M: K x p (ld ldm)
+mxw_status tall_gemm(mxw_problem* P, hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p,
+                     double alpha, double beta, double2* C) {
+  BlockWork& b = P->bw;
+  const int64_t n = P->L.ndof;
+  const zc za(alpha, 0.0), zb(beta, 0.0);
+  BLAS_CHECK(rocblas_set_stream(b.h, st));
+  BLAS_CHECK(rocblas_zgemm(b.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)n, p, K, &za,
+                           (const zc*)A, (rocblas_int)n, (const zc*)M, ldm, &zb, (zc*)C, (rocblas_int)n));
+  return MXW_OK;
+}
+
+// out = in S^{-1} with orthonormal columns (Cholesky QR twice); tmp: n x p.
+// have_gram: b.G already holds in^H in.
+mxw_status cholqr2(mxw_problem* P, hipStream_t st, const double2* in, double2* tmp, double2* out, int p,
+                   bool have_gram = false) {
+  BlockWork& b = P->bw;
+  if (!have_gram) TRY(gram(P, st, in, p, in, p, b.G));
+  launch_chol(st, p, b.G, b.R1, b.R1i, nullptr, nullptr, b.info);
+  TRY(tall_gemm(P, st, in, p, b.R1i, p, p, 1.0, 0.0, tmp));
+  TRY(gram(P, st, tmp, p, tmp, p, b.G));
+  launch_chol(st, p, b.G, b.R2, b.R2i, b.R1, b.S, b.info);
+  TRY(tall_gemm(P, st, tmp, p, b.R2i, p, p, 1.0, 0.0, out));
+  return MXW_OK;
+}
+
+mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_opts* opts, hipStream_t st,
+                       double2* X, int32_t* iters_out, double* relres_out) {
+  const int m = opts->restart;
+  const int64_t n = P->L.ndof;
+  TRY(ensure_krylov(P, p, m));
+  TRY(ensure_block(P, p, m));
+  KrylovWork& k = P->kw;
+  BlockWork& b = P->bw;
+  double* hbuf = k.host;
+  const int ldE = (m + 1) * p;
+  std::vector<double> bnorm(p), relres(p, 1.0);
+  k.history.assign(p, std::vector<double>());
+  launch_norm(st, n, B, n, k.npart, k.beta, p, nullptr);
+  HIP_CHECK(hipMemcpyAsync(hbuf, k.beta, sizeof(double) * p, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (int c = 0; c < p; ++c) {
+    bnorm[c] = hbuf[c];
+    if (!(bnorm[c] > 0)) {
+      set_error("block GMRES needs non-zero, independent right-hand sides");
+      return MXW_EINVAL;
+    }
+  }
+  HIP_CHECK(hipMemsetAsync(X, 0, sizeof(double2) * n * p, st));
+  HIP_CHECK(hipMemcpyAsync(k.Rv, B, sizeof(double2) * n * p, hipMemcpyDeviceToDevice, st));
+  b.reorth = 0;
+  int steps = 0;
+  bool conv = false, breakdown = false;
+  while (!conv && steps < opts->max_iters && !breakdown) {
+    // V_0 S0 = R
+    HIP_CHECK(hipMemsetAsync(b.info, 0, sizeof(int), st));
+    TRY(cholqr2(P, st, k.Rv, k.W, k.V, p));
+    launch_set_e(st, p, ldE, b.S, b.E);
+    int jd = 0;
+    for (int j = 0; j < m; ++j) {
+      double2* Vj = k.V + (int64_t)j * p * n;
+      double2* Zj = k.Z + (int64_t)j * p * n;
+      const int Q = (j + 1) * p;
+      apply_prec_dev(P, st, Vj, n, Zj, n, p, nullptr, k.YS, k.xbuf);
+      {
+        ScopedKernelTimer tm("spmv");
+        launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, n, k.W, n, nullptr, 0, p, nullptr);
+      }
+      // block classical Gram-Schmidt; a second pass where a column lost more
+      // than 1 - 1/sqrt(2) of its norm in the first
+      TRY(gram(P, st, k.W, p, k.W, p, b.G0));
+      TRY(gram(P, st, k.V, Q, k.W, p, b.H1));
+      TRY(tall_gemm(P, st, k.V, Q, b.H1, Q, p, -1.0, 1.0, k.W));
+      TRY(gram(P, st, k.W, p, k.W, p, b.G));
+      launch_reorth_check(st, p, b.G0, b.G, b.info + 1);
+      HIP_CHECK(hipMemcpyAsync(hbuf + p + 1, b.info + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      int again = 0;
+      std::memcpy(&again, hbuf + p + 1, sizeof(int));
+      if (again) {
+        ++b.reorth;
+        TRY(gram(P, st, k.V, Q, k.W, p, b.H2));
+        TRY(tall_gemm(P, st, k.V, Q, b.H2, Q, p, -1.0, 1.0, k.W));
+      }
+      // V_{j+1} S = W
+      TRY(cholqr2(P, st, k.W, k.Rv, k.V + (int64_t)(j + 1) * p * n, p, !again));
+      launch_bls_step(st, j, p, m, b.H1, again ? b.H2 : nullptr, b.S, b.Hc, b.T, b.Rls, b.E, b.est);
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipMemcpyAsync(hbuf, b.est, sizeof(double) * p, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipMemcpyAsync(hbuf + p, b.info, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      ++steps;
+      jd = j + 1;
+      bool all = true;
+      for (int c = 0; c < p; ++c) {
+        k.history[c].push_back(hbuf[c] / bnorm[c]);
+        if (!(hbuf[c] <= opts->tol * bnorm[c])) all = false;
+      }
+      int info = 0;
+      std::memcpy(&info, hbuf + p, sizeof(int));
+      if (info) breakdown = true;   // the new block lost rank
+      if (all || breakdown || steps >= opts->max_iters) break;
+    }
+    // X += Z Y; R = B - A X
+    launch_bls_solve(st, jd * p, p, m, b.Rls, b.E, b.Y);
+    TRY(tall_gemm(P, st, k.Z, jd * p, b.Y, m * p, p, 1.0, 1.0, X));
+    spmv_dev(P, st, X, k.Rv, B, p, nullptr);
+    launch_norm(st, n, k.Rv, n, k.npart, k.beta, p, nullptr);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(hbuf, k.beta, sizeof(double) * p, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    conv = true;
+    for (int c = 0; c < p; ++c) {
+      relres[c] = hbuf[c] / bnorm[c];
+      if (!(relres[c] <= opts->tol)) conv = false;
+    }
+    if (conv) breakdown = false;
+  }
+  for (int c = 0; c < p; ++c) {
+    if (iters_out) iters_out[c] = steps;
+    if (relres_out) relres_out[c] = relres[c];
+  }
+  if (conv) return MXW_OK;
+  if (breakdown) {
+    set_error("block Krylov breakdown (rank-deficient block) before the tolerance");
+    return MXW_EBREAKDOWN;
+  }
+  set_error("max_iters reached before the tolerance");
+  return MXW_ENOTCONV;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1136,13 +1363,21 @@ mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, cons
     set_error("invalid solve options (restart 1..200, max_iters >= 1, tol > 0)");
     return MXW_EINVAL;
   }
-  if (opts->krylov != MXW_KRYLOV_PSEUDOBLOCK) {
-    set_error("block GMRES is not available in this build");
+  if (opts->krylov != MXW_KRYLOV_PSEUDOBLOCK && opts->krylov != MXW_KRYLOV_BLOCK) {
+    set_error("unknown Krylov mode");
     return MXW_EINVAL;
   }
   if (!P->factored) {
     set_error("problem is not factorised");
     return MXW_EINVAL;
+  }
+  if (opts->krylov == MXW_KRYLOV_BLOCK) {
+    if (nrhs > max_block_p()) {
+      set_error("block GMRES takes at most 32 right-hand sides per block");
+      return MXW_EINVAL;
+    }
+    return block_solve(P, nrhs, (const double2*)b_dev, opts, (hipStream_t)stream, (double2*)x_dev, iters_out,
+                       relres_out);
   }
   hipStream_t st = (hipStream_t)stream;
   const int m = opts->restart, maxv = m + 1;

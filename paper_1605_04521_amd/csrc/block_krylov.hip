@@ -1,0 +1,374 @@
+// Block flexible GMRES over one shared Krylov space for all right-hand sides
+// (the block solver of Sec. 5): the small dense kernels.  The products with
+// the tall n x (j+1)p bases are plain complex GEMMs and go to rocBLAS (in
+// api.hip); here live the reductions of their split-K partial products, the
+// Cholesky factor of a Gram matrix (the block QR of a new basis block is a
+// Cholesky QR applied twice), the Householder update of the block Hessenberg
+// least-squares problem, and its back substitution.
+//
+// Layouts (all complex FP64, column-major):
+//   Hc  (m+1)p x p : new column block of the block Hessenberg matrix
+//   T   m x [2p x 2p] : per step, the unitary Q_j^H of the Householder QR of
+//                       the 2p x p window at rows jp..(j+2)p (applied to later
+//                       column blocks and to E)
+//   Rls mp x mp    : upper triangular factor of the block Hessenberg matrix
+//   E   (m+1)p x p : Q^H (S0; 0), the transformed right-hand side; the norms
+//                    of its rows (j+1)p..(j+2)p are the residual estimates.
+#include "device.h"
+#include "kernels.h"
+
+namespace mxw {
+
+constexpr int kMaxBlockP = 32;
+
+// H[idx] = sum over parts of part[t][idx] (+ H2 when accumulating)
+__global__ void k_gram_reduce(int64_t len, int nparts, const double2* __restrict__ part, double2* __restrict__ H) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= len) return;
+  double sr = 0.0, si = 0.0;
+  for (int t = 0; t < nparts; ++t) {
+    const double2 a = part[(int64_t)t * len + idx];
+    sr += a.x;
+    si += a.y;
+  }
+  H[idx] = make_double2(sr, si);
+}
+
+void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, nparts, part, H);
+}
+
+// Cholesky G = R^H R (R upper, p x p) and R^{-1}; optionally S = R Rprev.
+// info[0] = 1 if a pivot is not positive beyond rounding of the largest
+// diagonal entry (the block is rank deficient).
+__global__ void __launch_bounds__(256) k_chol(int p, const double2* __restrict__ G, double2* __restrict__ R,
+                                              double2* __restrict__ Rinv, const double2* __restrict__ Rprev,
+                                              double2* __restrict__ S, int* __restrict__ info) {
+  __shared__ double2 A[kMaxBlockP][kMaxBlockP + 1];   // A[row][col], becomes R
+  __shared__ double2 Ri[kMaxBlockP][kMaxBlockP + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < p * p; idx += 256) A[idx % p][idx / p] = G[idx];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = 0; i < p; ++i) dmax = fmax(dmax, A[i][i].x);
+  const double floor_ = 1e-15 * dmax * p;
+  for (int k = 0; k < p; ++k) {
+    if (tid == 0) {
+      double d = A[k][k].x;
+      if (!(d > floor_)) {
+        bad = 1;
+        d = fmax(floor_, 1e-300);
+      }
+      A[k][k] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    const double rkk = A[k][k].x;
+    // row k right of the diagonal, then the trailing Hermitian update
+    for (int c = k + 1 + tid; c < p; c += 256) A[k][c] = make_double2(A[k][c].x / rkk, A[k][c].y / rkk);
+    __syncthreads();
+    for (int idx = tid; idx < p * p; idx += 256) {
+      const int r = idx % p, c = idx / p;
+      if (r > k && c >= r) {
+        // A[r][c] -= conj(R[k][r]) R[k][c]
+        const double2 a = A[k][r], b = A[k][c];
+        A[r][c].x -= a.x * b.x + a.y * b.y;
+        A[r][c].y -= a.x * b.y - a.y * b.x;
+      }
+    }
+    __syncthreads();
+  }
+  // zero the strict lower part; R^{-1} by back substitution, one column per thread
+  for (int idx = tid; idx < p * p; idx += 256) {
+    const int r = idx % p, c = idx / p;
+    if (r > c) A[r][c] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (tid < p) {
+    const int c = tid;
+    for (int r = p - 1; r >= 0; --r) {
+      double xr = (r == c) ? 1.0 : 0.0, xi = 0.0;
+      if (r <= c) {
+        for (int q = r + 1; q <= c; ++q) {
+          const double2 a = A[r][q], y = Ri[q][c];
+          xr -= a.x * y.x - a.y * y.y;
+          xi -= a.x * y.y + a.y * y.x;
+        }
+        const double d = A[r][r].x;
+        xr /= d;
+        xi /= d;
+      }
+      Ri[r][c] = make_double2(r <= c ? xr : 0.0, r <= c ? xi : 0.0);
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < p * p; idx += 256) {
+    const int r = idx % p, c = idx / p;
+    R[idx] = A[r][c];
+    Rinv[idx] = Ri[r][c];
+    if (S) {
+      // S = R Rprev (both upper triangular)
+      double sr = 0.0, si = 0.0;
+      for (int q = r; q <= c; ++q) {
+        const double2 a = A[r][q], b = Rprev[(int64_t)c * p + q];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      S[idx] = make_double2(sr, si);
+    }
+  }
+  if (tid == 0 && bad) info[0] = 1;
+}
+
+void launch_chol(hipStream_t st, int p, const double2* G, double2* R, double2* Rinv, const double2* Rprev,
+                 double2* S, int* info) {
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, st, p, G, R, Rinv, Rprev, S, info);
+}
+
+// E = 0 except E[0:p, 0:p] = S0
+__global__ void k_set_e(int p, int ldE, const double2* __restrict__ S0, double2* __restrict__ E) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ldE * p) return;
+  const int r = idx % ldE, c = idx / ldE;
+  E[idx] = r < p ? S0[c * p + r] : make_double2(0.0, 0.0);
+}
+
+void launch_set_e(hipStream_t st, int p, int ldE, const double2* S0, double2* E) {
+  hipLaunchKernelGGL(k_set_e, dim3((ldE * p + 255) / 256), dim3(256), 0, st, p, ldE, S0, E);
+}
+
+// Y_out[2p x p] = M[2p x 2p] Y_in[2p x p] for a window of rows in LDS.
+__device__ void window_product(int p, const double2* __restrict__ M, const double2 (*Win)[kMaxBlockP + 1],
+                               double2 (*Wout)[kMaxBlockP + 1]) {
+  const int p2 = 2 * p;
+  for (int idx = threadIdx.x; idx < p2 * p; idx += blockDim.x) {
+    const int r = idx % p2, c = idx / p2;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < p2; ++k) {
+      const double2 a = M[(int64_t)k * p2 + r], b = Win[k][c];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    Wout[r][c] = make_double2(sr, si);
+  }
+}
+
+// Step j of the block Hessenberg least squares (one workgroup):
+//   1. Hc = [H1 + H2 (rows 0..(j+1)p); S (rows (j+1)p..(j+2)p)];
+//   2. apply Q_i^H of the earlier steps to their windows of Hc;
+//   3. Householder QR of the window rows jp..(j+2)p (2p x p), reflectors
+//      I - 2 v v^H / (v^H v) with v_0 chosen so that the diagonal is
+//      -e^{i arg x_0} |x|; Q_j^H = H_{p-1} ... H_0 stored in T_j;
+//   4. E window <- Q_j^H E window; R column block stored; est = row norms.
+__global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const double2* __restrict__ H1,
+                                                  const double2* __restrict__ H2, const double2* __restrict__ S,
+                                                  double2* __restrict__ Hc, double2* __restrict__ T,
+                                                  double2* __restrict__ Rls, double2* __restrict__ E,
+                                                  double* __restrict__ est) {
+  __shared__ double2 A[2 * kMaxBlockP][kMaxBlockP + 1];
+  __shared__ double2 B[2 * kMaxBlockP][kMaxBlockP + 1];
+  __shared__ double2 Qt[2 * kMaxBlockP][2 * kMaxBlockP + 1];
+  __shared__ double2 vh[2 * kMaxBlockP];
+  __shared__ double tau_s, red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p2 = 2 * p, ld = (m + 1) * p, Q = (j + 1) * p, ldR = m * p;
+  // 1. assemble the column block
+  for (int idx = tid; idx < (Q + p) * p; idx += 256) {
+    const int r = idx % (Q + p), c = idx / (Q + p);
+    double2 v;
+    if (r < Q) {
+      const double2 a = H1[(int64_t)c * Q + r];
+      const double2 b = H2 ? H2[(int64_t)c * Q + r] : make_double2(0.0, 0.0);
+      v = make_double2(a.x + b.x, a.y + b.y);
+    } else {
+      v = S[(int64_t)c * p + (r - Q)];
+    }
+    Hc[(int64_t)c * ld + r] = v;
+  }
+  __syncthreads();
+  // 2. earlier transforms, window by window (windows overlap: in order)
+  for (int i = 0; i < j; ++i) {
+    for (int idx = tid; idx < p2 * p; idx += 256) {
+      const int r = idx % p2, c = idx / p2;
+      A[r][c] = Hc[(int64_t)c * ld + i * p + r];
+    }
+    __syncthreads();
+    window_product(p, T + (int64_t)i * p2 * p2, A, B);
+    __syncthreads();
+    for (int idx = tid; idx < p2 * p; idx += 256) {
+      const int r = idx % p2, c = idx / p2;
+      Hc[(int64_t)c * ld + i * p + r] = B[r][c];
+    }
+    __syncthreads();
+  }
+  // 3. Householder QR of the window at rows jp..(j+2)p
+  for (int idx = tid; idx < p2 * p; idx += 256) {
+    const int r = idx % p2, c = idx / p2;
+    A[r][c] = Hc[(int64_t)c * ld + j * p + r];
+  }
+  for (int idx = tid; idx < p2 * p2; idx += 256) {
+    const int r = idx % p2, c = idx / p2;
+    Qt[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < p; ++k) {
+    // norm of A[k:, k] (wave 0)
+    if (wave == 0) {
+      double s2 = 0.0;
+      for (int r = k + lane; r < p2; r += 64) s2 += A[r][k].x * A[r][k].x + A[r][k].y * A[r][k].y;
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        const double nrm = sqrt(s2);
+        const double2 x0 = A[k][k];
+        const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+        double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+        const double2 alpha = make_double2(-ph.x * nrm, -ph.y * nrm);
+        const double vv = 2.0 * nrm * (nrm + ax0);
+        tau_s = vv > 0.0 ? 2.0 / vv : 0.0;
+        red[0] = alpha.x;
+        red[1] = alpha.y;
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < p2; r += 256) {
+      double2 v = make_double2(0.0, 0.0);
+      if (r > k) v = A[r][k];
+      if (r == k) v = make_double2(A[k][k].x - red[0], A[k][k].y - red[1]);
+      vh[r] = v;
+    }
+    __syncthreads();
+    const double tau = tau_s;
+    // apply to the remaining columns of A and to every column of Qt
+    for (int c = tid; c < p + p2; c += 256) {
+      double2* col = nullptr;
+      bool isA = c < p;
+      if (isA && c <= k) continue;
+      double wr = 0.0, wi = 0.0;   // w = v^H col
+      for (int r = k; r < p2; ++r) {
+        const double2 x = isA ? A[r][c] : Qt[r][c - p];
+        wr += vh[r].x * x.x + vh[r].y * x.y;
+        wi += vh[r].x * x.y - vh[r].y * x.x;
+      }
+      wr *= tau;
+      wi *= tau;
+      for (int r = k; r < p2; ++r) {
+        const double2 v = vh[r];
+        const double dr = v.x * wr - v.y * wi, di = v.x * wi + v.y * wr;
+        if (isA) {
+          A[r][c].x -= dr;
+          A[r][c].y -= di;
+        } else {
+          Qt[r][c - p].x -= dr;
+          Qt[r][c - p].y -= di;
+        }
+      }
+      (void)col;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      A[k][k] = make_double2(red[0], red[1]);
+    }
+    for (int r = k + 1 + tid; r < p2; r += 256) A[r][k] = make_double2(0.0, 0.0);
+    __syncthreads();
+  }
+  // store Q_j^H
+  for (int idx = tid; idx < p2 * p2; idx += 256) {
+    const int r = idx % p2, c = idx / p2;
+    T[(int64_t)j * p2 * p2 + idx] = Qt[r][c];
+  }
+  // R column block: rows 0..jp from Hc, rows jp..(j+1)p from A
+  for (int idx = tid; idx < Q * p; idx += 256) {
+    const int r = idx % Q, c = idx / Q;
+    Rls[(int64_t)(j * p + c) * ldR + r] = r < j * p ? Hc[(int64_t)c * ld + r] : A[r - j * p][c];
+  }
+  // 4. E window
+  for (int idx = tid; idx < p2 * p; idx += 256) {
+    const int r = idx % p2, c = idx / p2;
+    B[r][c] = E[(int64_t)c * ld + j * p + r];
+  }
+  __syncthreads();
+  {
+    for (int idx = tid; idx < p2 * p; idx += 256) {
+      const int r = idx % p2, c = idx / p2;
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < p2; ++k) {
+        const double2 a = Qt[r][k], b = B[k][c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      A[r][c] = make_double2(sr, si);
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < p2 * p; idx += 256) {
+    const int r = idx % p2, c = idx / p2;
+    E[(int64_t)c * ld + j * p + r] = A[r][c];
+  }
+  if (tid < p) {
+    double s2 = 0.0;
+    for (int r = p; r < p2; ++r) s2 += A[r][tid].x * A[r][tid].x + A[r][tid].y * A[r][tid].y;
+    est[tid] = sqrt(s2);
+  }
+}
+
+void launch_bls_step(hipStream_t st, int j, int p, int m, const double2* H1, const double2* H2, const double2* S,
+                     double2* Hc, double2* T, double2* Rls, double2* E, double* est) {
+  hipLaunchKernelGGL(k_bls_step, dim3(1), dim3(256), 0, st, j, p, m, H1, H2, S, Hc, T, Rls, E, est);
+}
+
+// Y = R^{-1} E[0:jp, :] (R = Rls[0:jp, 0:jp], upper); Y has leading dimension m p.
+__global__ void __launch_bounds__(256) k_bls_solve(int jp, int p, int m, const double2* __restrict__ Rls,
+                                                   const double2* __restrict__ E, double2* __restrict__ Y) {
+  const int tid = threadIdx.x, ldR = m * p, ldE = (m + 1) * p;
+  for (int idx = tid; idx < jp * p; idx += 256) {
+    const int r = idx % jp, c = idx / jp;
+    Y[(int64_t)c * ldR + r] = E[(int64_t)c * ldE + r];
+  }
+  __syncthreads();
+  __shared__ double2 q[kMaxBlockP];
+  for (int i = jp - 1; i >= 0; --i) {
+    // Y[i][c] /= R[i][i]; then Y[0:i][c] -= R[0:i][i] Y[i][c]
+    if (tid < p) {
+      const double2 d = Rls[(int64_t)i * ldR + i];
+      const double dd = d.x * d.x + d.y * d.y;
+      const double2 yi = Y[(int64_t)tid * ldR + i];
+      const double2 v = make_double2((yi.x * d.x + yi.y * d.y) / dd, (yi.y * d.x - yi.x * d.y) / dd);
+      Y[(int64_t)tid * ldR + i] = v;
+      q[tid] = v;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < i * p; idx += 256) {
+      const int r = idx % i, c = idx / i;
+      const double2 a = Rls[(int64_t)i * ldR + r], v = q[c];
+      Y[(int64_t)c * ldR + r].x -= a.x * v.x - a.y * v.y;
+      Y[(int64_t)c * ldR + r].y -= a.x * v.y + a.y * v.x;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_bls_solve(hipStream_t st, int jp, int p, int m, const double2* Rls, const double2* E, double2* Y) {
+  hipLaunchKernelGGL(k_bls_solve, dim3(1), dim3(256), 0, st, jp, p, m, Rls, E, Y);
+}
+
+// Reorthogonalisation test of block classical Gram-Schmidt (the criterion of
+// Daniel, Gragg, Kaufman and Stewart, per column): a second pass is needed if
+// some column kept less than 1/sqrt(2) of its norm in the first pass.
+__global__ void k_reorth_check(int p, const double2* __restrict__ G0, const double2* __restrict__ G1,
+                               int* __restrict__ flag) {
+  const int c = threadIdx.x;
+  int need = 0;
+  if (c < p) need = !(G1[(int64_t)c * p + c].x >= 0.5 * G0[(int64_t)c * p + c].x);
+  need = __any(need);
+  if (c == 0) flag[0] = need;
+}
+
+void launch_reorth_check(hipStream_t st, int p, const double2* G0, const double2* G1, int* flag) {
+  hipLaunchKernelGGL(k_reorth_check, dim3(1), dim3(64), 0, st, p, G0, G1, flag);
+}
+
+int max_block_p() { return kMaxBlockP; }
+
+}  // namespace mxw

@@ -126,6 +126,18 @@ int multi_chunk_cols();
 void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const int64_t* pos, const double2* ys,
                        int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active);
 
+// block GMRES: split-K Gram reduction, Cholesky + inverse of a p x p Gram
+// matrix, block Hessenberg least-squares step and back substitution
+void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H);
+void launch_chol(hipStream_t st, int p, const double2* G, double2* R, double2* Rinv, const double2* Rprev,
+                 double2* S, int* info);
+void launch_set_e(hipStream_t st, int p, int ldE, const double2* S0, double2* E);
+void launch_bls_step(hipStream_t st, int j, int p, int m, const double2* H1, const double2* H2, const double2* S,
+                     double2* Hc, double2* T, double2* Rls, double2* E, double* est);
+void launch_bls_solve(hipStream_t st, int jp, int p, int m, const double2* Rls, const double2* E, double2* Y);
+void launch_reorth_check(hipStream_t st, int p, const double2* G0, const double2* G1, int* flag);
+int max_block_p();
+
 void launch_spmv(hipStream_t st, int group, int64_t n, const int64_t* rowptr, const int* cols, const double2* vals,
                  const double2* x, int64_t xstride, double2* y, int64_t ystride, const double2* b, int64_t bstride,
                  int ncol, const int* active);

@@ -276,3 +276,46 @@ def test_multi_column_spmv():
     for c in range(11):
         y1 = to_np(P.apply_A(Xt[c:c + 1]))[0]
         assert np.linalg.norm(Y[c] - y1) <= 1e-15 * np.linalg.norm(y1), c
+
+
+@pytest.mark.parametrize("restart", [50, 4])
+def test_block_gmres_matches_oracle(restart):
+    """Block FGMRES (one Krylov space for 4 right-hand sides; block CGS2 and
+    Cholesky QR on the GPU, Householder in the oracle) against the oracle's
+    block FGMRES: the same block step count within +-1 and the same E within
+    1e-6; with restart 4 several cycles run."""
+    prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2, n_sources=4)
+    say(f"[gpu] block GMRES restart={restart} vs oracle")
+    orc = OracleSolver.from_problem(prob)
+    Bo = np.stack([orc.rhs(s) for s in prob.sources], axis=1)
+    Xo, steps_o, rel_o, ok = orc.solve_block(Bo, restart=restart)
+    assert ok
+    P = Problem.from_problem(prob)
+    X, it, rr, st = P.solve(prob.sources, krylov=B.MXW_KRYLOV_BLOCK, restart=restart)
+    X = to_np(X)
+    say(f"   block steps gpu={it[0]} oracle={steps_o} relres={rr.max():.2e}")
+    assert np.all(it == it[0]) and abs(int(it[0]) - steps_o) <= 1
+    assert np.all(rr <= 1e-8)
+    for c in range(4):
+        b = Bo[:, c]
+        assert np.linalg.norm(b - orc.A @ X[c]) <= 1.01e-8 * np.linalg.norm(b)
+        assert np.linalg.norm(X[c] - Xo[:, c]) <= 1e-6 * np.linalg.norm(Xo[:, c]), c
+    # the same solution as the pseudo-block path
+    Xp, itp, _, _ = P.solve(prob.sources)
+    assert np.linalg.norm(to_np(Xp) - X) <= 1e-6 * np.linalg.norm(X)
+    assert it[0] <= itp.max()
+
+
+def test_block_gmres_invalid_inputs():
+    prob = gen.chamber_problem(n=4, degree=1, n_sub=2, overlap=1, n_sources=2)
+    say("[gpu] block GMRES invalid inputs")
+    P = Problem.from_problem(prob)
+    b = P.rhs(prob.sources)
+    b[1].zero_()
+    with pytest.raises(B.MxwError) as e:
+        P.solve_rhs(b, krylov=B.MXW_KRYLOV_BLOCK)
+    assert e.value.status == B.MXW_EINVAL
+    big = torch.zeros((33, P.ndof), dtype=torch.complex128, device="cuda")
+    with pytest.raises(B.MxwError) as e:
+        P.solve_rhs(big, krylov=B.MXW_KRYLOV_BLOCK)
+    assert e.value.status == B.MXW_EINVAL
