@@ -368,6 +368,7 @@ uint64_t factor_bytes(const Layout& L, int precision) {
   for (int s = 0; s < L.n_sub; ++s) {
     int64_t n = L.sub_dof_ptr[s + 1] - L.sub_dof_ptr[s];
     e += 2 * (uint64_t)round_ld(n) * n;
+    e += 2 * (uint64_t)n * kLuNB;   // LU block-column scratch
   }
   return e * (precision == MXW_MIXED ? 4 : 8);
 }
@@ -900,7 +901,8 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
   P->info = M.alloc<int>(L.n_sub);
   const size_t rsz = mixed ? 4 : 8;
   P->F = M.alloc<unsigned char>(P->factor_elems * rsz);
-  P->lu_scratch = M.alloc<unsigned char>((size_t)L.n_sub * 2 * kLuNB * kLuNB * rsz);
+  // the LU's row-major copy of the current block column, per subdomain: 2 planes x n_s x 32
+  P->lu_scratch = M.alloc<unsigned char>((size_t)L.sum_ns * 2 * kLuNB * rsz);
   P->AT = M.alloc<double2>((size_t)L.nt * nloc * nloc);
   P->vals = M.alloc<double2>(L.cols.size());
   if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->vals || !P->eps || !P->imp_beta ||

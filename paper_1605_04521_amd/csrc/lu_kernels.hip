@@ -2,35 +2,43 @@
 // (the factorised local solves A_s^{-1} of ORAS, Sec. 4), in FP64 or FP32.
 //
 // Storage per subdomain: column-major, leading dimension ld, real plane then
-// imaginary plane.  One workgroup (4 wavefronts) factorises one matrix with a
-// right-looking blocked algorithm of panel width NB:
-//   1. panel: unblocked LU of columns [k, k+NB) with pivot search on
-//      |re| + |im| (lowest row on ties); the search for the next column is
-//      fused into the rank-1 update of the current one;
-//   2. the panel's row interchanges are applied to the other columns as one
-//      net permutation of the affected rows;
-//   3. L11^{-1} (unit lower) and U11^{-1} are formed in LDS; U12 = L11^{-1} A12
-//      and A22 -= L21 U12 run as complex GEMMs on MFMA (4 real products each),
-//      accumulating straight into the C tile held in the MFMA accumulators;
-//   4. the diagonal block is replaced by [L11^{-1} strict lower | U11^{-1}],
-//      which turns the diagonal solves of the triangular sweeps into products.
+// imaginary plane.  One workgroup (4 wavefronts) factorises one matrix, all
+// matrices in one launch (largest first).  Left-looking, block columns of
+// width NB = 32; for block column J (columns [j0, j0 + 32)):
+//   A. the column block is copied to a row-major scratch X (n x 32);
+//   B. the factored part is applied to it: for the 32-row blocks K < J the
+//      forward substitution X_K = L_KK^{-1} (X_K - L_{K,<K} X_{<K}), for the
+//      rows below X_rows -= L_{rows,<j0} X_{<j0} -- the same blocked sweep as
+//      the multi-column local solve (64 rows per pass over the factor, the K
+//      range split over the waves, 16x16x4 MFMA products, triangular blocks
+//      as MFMA tile products); each factor entry left of j0 is read once per
+//      block column, and the block column's accumulators never leave the chip
+//      within a pass;
+//   C. X is written back (rows < j0 are U, rows >= j0 the updated panel);
+//   D. panel: unblocked LU of rows [j0, n) with pivot search on |re| + |im|
+//      (lowest row on ties), the search for the next column fused into the
+//      rank-1 update of the current one;
+//   E. the panel's row interchanges are applied to every other column as one
+//      net permutation;
+//   F. the diagonal block is replaced by [L_JJ^{-1} strict lower | U_JJ^{-1}],
+//      which turns the diagonal solves of every later sweep into products.
 // perm receives the row permutation: (P A)[i] = A[perm[i]].
 #include "device.h"
 #include "kernels.h"
+#include "sweep.h"
 
 namespace mxw {
 
 constexpr int kPad = 4;
 
 template <typename R, int NB>
-struct LuSmem {
-  // GEMM tiles: A tile [k][row], B tile [k][col].  While the diagonal block
-  // is inverted, Are/Aim[c][0..NB) hold its copy (column c) and
-  // Are/Aim[c][NB..2NB) column c of L11^{-1}; Bre/Bim[c][0..NB) column c of U11^{-1}.
-  R Are[NB][64 + kPad];
-  R Aim[NB][64 + kPad];
-  R Bre[NB][64 + kPad];
-  R Bim[NB][64 + kPad];
+struct PanelSmem {
+  // inverse workspace: Are/Aim[c][0..NB) the diagonal block (column c),
+  // Are/Aim[c][NB..2NB) column c of L11^{-1}; Bre/Bim[c][0..NB) column c of U11^{-1}
+  R Are[NB][2 * NB + kPad];
+  R Aim[NB][2 * NB + kPad];
+  R Bre[NB][NB + kPad];
+  R Bim[NB][NB + kPad];
   double rv[4];
   int ri[4];
   R ur[NB], ui[NB];
@@ -38,6 +46,19 @@ struct LuSmem {
   int src[2 * NB], dst[2 * NB];
   int rows[2 * NB], cont[2 * NB];
   int npairs;
+};
+
+template <typename R, int NB>
+struct SweepSmem {
+  R Tr[2 * NB][NB + 1], Ti[2 * NB][NB + 1];        // T of the 64-row pass
+  R Br[3][NB][NB + 1], Bi[3][NB][NB + 1];          // first diagonal inverse, coupling block, second diagonal inverse
+  R Yr[NB][NB + 1], Yi[NB][NB + 1];                // solution of the first block
+};
+
+template <typename R, int NB>
+union LuSmem {
+  PanelSmem<R, NB> p;
+  SweepSmem<R, NB> s;
 };
 
 __device__ __forceinline__ void wave_argmax(double& v, int& i) {
@@ -52,125 +73,183 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
   }
 }
 
-// C[M x N] = (sub ? C - A B : A B); A is M x NB (lda), B is NB x N (ldb), all
-// column-major complex split planes.  The product is formed transposed
-// (D = B^T A^T on MFMA) so that each lane's outputs run down a column of C;
-// the accumulators start from C (sub) and B enters with the sign folded in.
+// Step B for block column j0: the 64-row passes over the factored columns.
 template <typename R, int NB>
-__device__ void wg_cgemm(int M, int N, const R* __restrict__ Ar, const R* __restrict__ Ai, int64_t lda,
-                         const R* Br, const R* Bi, int64_t ldb, R* Cr, R* Ci, int64_t ldc, bool sub,
-                         LuSmem<R, NB>& sm) {
+__device__ void apply_factored(SweepSmem<R, NB>& sm, int n, int ld, int j0, __amdgpu_buffer_rsrc_t fr,
+                               __amdgpu_buffer_rsrc_t fi, R* __restrict__ Xr, R* __restrict__ Xi,
+                               __amdgpu_buffer_rsrc_t xrr, __amdgpu_buffer_rsrc_t xir) {
+  constexpr int PC = NB, SB = 2 * NB, KU = 8;
   typedef typename Mfma<R>::acc_t acc_t;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
-  const int li = lane & 15, lk = lane >> 4;
-  const R sgn = sub ? R(-1) : R(1);
-  for (int n0 = 0; n0 < N; n0 += 64) {
+  const int wave = threadIdx.x >> 6;
+  const int rh = wave & 1, kh = wave >> 1;
+  const int nsb = (n + SB - 1) / SB;
+  for (int sb = 0; sb < nsb; ++sb) {
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int r0 = sb * SB, rn = min(SB, n - r0);
+    const int k_hi = min(r0, j0);                 // product over factored columns [0, k_hi)
+    const bool solve0 = r0 < j0, solve1 = r0 + NB < j0;   // blocks left of j0 take the triangular solve
+    if (k_hi == 0 && !solve0) continue;           // nothing factored applies to these rows
+    const int n0 = min(NB, rn), n1 = max(0, rn - NB);
+    // prefetch the triangular blocks (first diagonal, coupling, second diagonal)
+    R pbr[3][4], pbi[3][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+      const int rows[3] = {0, 1, 1}, cols[3] = {0, 0, 1};
+      const int rlim[3] = {n0, n1, n1}, clim[3] = {n0, n0, n1};
+      const bool use[3] = {solve0, solve0, solve1};
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const bool in = use[m] && r < rlim[m] && c < clim[m];
+        const int o = in ? ((r0 + cols[m] * NB + c) * ld + r0 + rows[m] * NB + r) * (int)sizeof(R) : kOob;
+        pbr[m][j] = BufLoad<R>::at(fr, o);
+        pbi[m][j] = BufLoad<R>::at(fi, o);
+      }
+    }
+    acc_t pre[2][2], pim[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        pre[rt][ct] = acc_t{0, 0, 0, 0};
+        pim[rt][ct] = acc_t{0, 0, 0, 0};
+      }
+    bool row_ok[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) row_ok[rt] = rh * NB + rt * 16 + li < rn;
+    const int arow = r0 + rh * NB + li;
+    for (int k0 = 4 * KU * kh; k0 < k_hi; k0 += 8 * KU) {
+      Slice<R, KU, PC> sl;
+      sl.load(fr, fi, xrr, xir, ld, arow, row_ok, k0, k_hi, lk, li);
+      __builtin_amdgcn_sched_barrier(0);
+      sl.product(pre, pim);
+    }
+    // T = X - product; stage the blocks: diagonal inverses as full matrices
+    // (unit lower) for solved blocks, identity otherwise; coupling or zero
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
+      const int o = r < rn ? (r0 * PC + idx) * (int)sizeof(R) : kOob;
+      sm.Tr[r][c] = BufLoad<R>::at(xrr, o);
+      sm.Ti[r][c] = BufLoad<R>::at(xir, o);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        R vr = pbr[m][j], vi = pbi[m][j];
+        if (m != 1) {
+          const int bn = m == 0 ? n0 : n1;
+          vr = c < r ? vr : (c == r && r < bn ? R(1) : R(0));
+          vi = c < r ? vi : R(0);
+        }
+        sm.Br[m][r][c] = vr;
+        sm.Bi[m][r][c] = vi;
+      }
+    }
     __syncthreads();
-    for (int idx = tid; idx < NB * 64; idx += 256) {
-      const int kk = idx % NB, cc = idx / NB, c = n0 + cc;
-      R vr = R(0), vi = R(0);
-      if (c < N) {
-        vr = sgn * Br[(int64_t)c * ldb + kk];
-        vi = sgn * Bi[(int64_t)c * ldb + kk];
-      }
-      sm.Bre[kk][cc] = vr;
-      sm.Bim[kk][cc] = vi;
-    }
-    for (int m0 = 0; m0 < M; m0 += 64) {
-      acc_t dre[2][2], dim[2][2];
+    for (int phase = 1; phase >= 0; --phase) {
+      if (kh == phase) {
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+        for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+          for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int col = n0 + wc * 32 + c * 16 + Mfma<R>::row(lane, v);
-            const int row = m0 + wr * 32 + r * 16 + li;
-            R a = R(0), b = R(0);
-            if (sub && row < M && col < N) {
-              a = Cr[(int64_t)col * ldc + row];
-              b = Ci[(int64_t)col * ldc + row];
+            for (int q = 0; q < 4; ++q) {
+              const int r = rh * NB + rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
+              sm.Tr[r][c] -= pre[rt][ct][q];
+              sm.Ti[r][c] -= pim[rt][ct][q];
             }
-            dre[c][r][v] = a;
-            dim[c][r][v] = b;
-          }
-      for (int idx = tid; idx < 64 * NB; idx += 256) {
-        const int rr = idx & 63, kk = idx >> 6, r = m0 + rr;
-        R vr = R(0), vi = R(0);
-        if (r < M) {
-          vr = Ar[(int64_t)kk * lda + r];
-          vi = Ai[(int64_t)kk * lda + r];
-        }
-        sm.Are[kk][rr] = vr;
-        sm.Aim[kk][rr] = vi;
       }
       __syncthreads();
-#pragma unroll 2
-      for (int k0 = 0; k0 < NB; k0 += 4) {
-        const int kk = k0 + lk;
-        R bre[2], bim[2], are[2], aim[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          bre[c] = sm.Bre[kk][wc * 32 + c * 16 + li];
-          bim[c] = sm.Bim[kk][wc * 32 + c * 16 + li];
-          are[c] = sm.Are[kk][wr * 32 + c * 16 + li];
-          aim[c] = sm.Aim[kk][wr * 32 + c * 16 + li];
-        }
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int r = 0; r < 2; ++r) {
-            dre[c][r] = Mfma<R>::op(bre[c], are[r], dre[c][r]);
-            dre[c][r] = Mfma<R>::op(-bim[c], aim[r], dre[c][r]);
-            dim[c][r] = Mfma<R>::op(bre[c], aim[r], dim[c][r]);
-            dim[c][r] = Mfma<R>::op(bim[c], are[r], dim[c][r]);
-          }
-      }
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int col = n0 + wc * 32 + c * 16 + Mfma<R>::row(lane, v);
-            const int row = m0 + wr * 32 + r * 16 + li;
-            if (row < M && col < N) {
-              Cr[(int64_t)col * ldc + row] = dre[c][r][v];
-              Ci[(int64_t)col * ldc + row] = dim[c][r][v];
-            }
-          }
-      __syncthreads();
     }
+    // Y0 = M0 T0; T1 -= C Y0; X1 = M1 T1 (M identity and C zero where the
+    // blocks are not yet factored)
+    const int orow = (wave & 1) * 16, ocol = (wave >> 1) * 16 + li;
+    {
+      acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+      tile_product<R, NB, PC>(sm.Br[0], sm.Bi[0], sm.Tr, sm.Ti, lane, wave, yre, yim);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = orow + Mfma<R>::row(lane, q);
+        sm.Yr[r][ocol] = yre[q];
+        sm.Yi[r][ocol] = yim[q];
+        if (r < n0) {
+          Xr[(int64_t)(r0 + r) * PC + ocol] = yre[q];
+          Xi[(int64_t)(r0 + r) * PC + ocol] = yim[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (n1 > 0) {
+      acc_t cre = acc_t{0, 0, 0, 0}, cim = acc_t{0, 0, 0, 0};
+      tile_product<R, NB, PC>(sm.Br[1], sm.Bi[1], sm.Yr, sm.Yi, lane, wave, cre, cim);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = orow + Mfma<R>::row(lane, q);
+        sm.Tr[NB + r][ocol] -= cre[q];
+        sm.Ti[NB + r][ocol] -= cim[q];
+      }
+      __syncthreads();
+      acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+      tile_product<R, NB, PC>(sm.Br[2], sm.Bi[2], sm.Tr + NB, sm.Ti + NB, lane, wave, yre, yim);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = orow + Mfma<R>::row(lane, q);
+        if (r < n1) {
+          Xr[(int64_t)(r0 + NB + r) * PC + ocol] = yre[q];
+          Xi[(int64_t)(r0 + NB + r) * PC + ocol] = yim[q];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <typename R, int NB>
-__global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t* __restrict__ foff,
-                                               const int* __restrict__ nsz, const int* __restrict__ lds,
-                                               int* __restrict__ perm, const int64_t* __restrict__ poff,
-                                               R* __restrict__ scratch, int* __restrict__ info,
-                                               const int* __restrict__ order) {
-  static_assert(2 * NB <= 64 + kPad, "inverse workspace must fit the tile rows");
-  __shared__ LuSmem<R, NB> sm;
+__global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __restrict__ foff,
+                                            const int* __restrict__ nsz, const int* __restrict__ lds,
+                                            int* __restrict__ perm, const int64_t* __restrict__ poff,
+                                            R* __restrict__ xscr, int* __restrict__ info,
+                                            const int* __restrict__ order) {
+  static_assert(NB == 32, "the sweep tiles assume 32-wide blocks");
+  __shared__ LuSmem<R, NB> smu;
+  PanelSmem<R, NB>& sm = smu.p;
   const int s = order ? order[blockIdx.x] : blockIdx.x;
   const int n = nsz[s];
   const int64_t ld = lds[s];
   R* Ar = F + foff[s];
   R* Ai = Ar + ld * n;
   int* P = perm + poff[s];
-  R* Wr = scratch + (int64_t)blockIdx.x * 2 * NB * NB;   // L11^{-1} (unit lower, full NB x NB)
-  R* Wi = Wr + NB * NB;
+  R* Xr = xscr + 2 * poff[s] * NB;   // row-major n x NB block column
+  R* Xi = Xr + (int64_t)n * NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const __amdgpu_buffer_rsrc_t fr = plane_rsrc(Ar, ld * n * (int64_t)sizeof(R));
+  const __amdgpu_buffer_rsrc_t fi = plane_rsrc(Ai, ld * n * (int64_t)sizeof(R));
+  const __amdgpu_buffer_rsrc_t xrr = plane_rsrc(Xr, (int64_t)n * NB * sizeof(R));
+  const __amdgpu_buffer_rsrc_t xir = plane_rsrc(Xi, (int64_t)n * NB * sizeof(R));
   for (int i = tid; i < n; i += 256) P[i] = i;
   int first_zero = 0;
   // singularity threshold: |pivot| <= n u max|A_s| (FP64) or u max|A_s| (FP32)
   double tiny;
   {
     double amax = 0.0;
-    for (int c = 0; c < n; ++c)
-      for (int i = tid; i < n; i += 256)
-        amax = fmax(amax, fabs((double)Ar[(int64_t)c * ld + i]) + fabs((double)Ai[(int64_t)c * ld + i]));
+    const int nn = n * n;
+    for (int e0 = tid; e0 < nn; e0 += 8 * 256) {
+      R vr[8], vi[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {   // 8 loads in flight per thread
+        const int e = e0 + u * 256;
+        const int o = e < nn ? ((e / n) * (int)ld + e % n) * (int)sizeof(R) : kOob;
+        vr[u] = BufLoad<R>::at(fr, o);
+        vi[u] = BufLoad<R>::at(fi, o);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) amax = fmax(amax, fabs((double)vr[u]) + fabs((double)vi[u]));
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
     if (lane == 0) sm.rv[wave] = amax;
@@ -180,8 +259,52 @@ __global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t*
     __syncthreads();
   }
 
+
   for (int k = 0; k < n; k += NB) {
     const int kb = min(NB, n - k);
+    if (k > 0) {
+      // ---- A. block column to the row-major scratch, 64 rows at a time
+      // through LDS (coalesced on both sides)
+      SweepSmem<R, NB>& ts = smu.s;
+      for (int i0 = 0; i0 < n; i0 += 2 * NB) {
+        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
+          const int r = idx % (2 * NB), c = idx / (2 * NB);
+          const bool in = c < kb && i0 + r < n;
+          ts.Tr[r][c] = in ? Ar[(int64_t)(k + c) * ld + i0 + r] : R(0);
+          ts.Ti[r][c] = in ? Ai[(int64_t)(k + c) * ld + i0 + r] : R(0);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
+          const int c = idx % NB, r = idx / NB;
+          if (i0 + r < n) {
+            Xr[(int64_t)(i0 + r) * NB + c] = ts.Tr[r][c];
+            Xi[(int64_t)(i0 + r) * NB + c] = ts.Ti[r][c];
+          }
+        }
+        __syncthreads();
+      }
+      // ---- B. apply the factored columns
+      apply_factored<R, NB>(smu.s, n, (int)ld, k, fr, fi, Xr, Xi, xrr, xir);
+      // ---- C. back to the factor storage, through LDS
+      for (int i0 = 0; i0 < n; i0 += 2 * NB) {
+        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
+          const int c = idx % NB, r = idx / NB;
+          if (i0 + r < n) {
+            ts.Tr[r][c] = Xr[(int64_t)(i0 + r) * NB + c];
+            ts.Ti[r][c] = Xi[(int64_t)(i0 + r) * NB + c];
+          }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
+          const int r = idx % (2 * NB), c = idx / (2 * NB);
+          if (c < kb && i0 + r < n) {
+            Ar[(int64_t)(k + c) * ld + i0 + r] = ts.Tr[r][c];
+            Ai[(int64_t)(k + c) * ld + i0 + r] = ts.Ti[r][c];
+          }
+        }
+        __syncthreads();
+      }
+    }
     // ---- 1. panel factorisation; (best, bi): this thread's candidate pivot
     double best = -1.0;
     int bi = 0x7fffffff;
@@ -230,23 +353,42 @@ __global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t*
       const R rr = den > R(0) ? pr / den : R(0), ri = den > R(0) ? -pi / den : R(0);
       best = -1.0;
       bi = 0x7fffffff;
+      // scale column j and update the columns right of it, one row per
+      // thread at a time: the row's entries of 16 columns are loaded together
+      // (branch-free buffer accesses, masked columns out of range), updated
+      // in registers and stored
       for (int i = j + 1 + tid; i < n; i += 256) {
-        const R ar = Ar[(int64_t)j * ld + i], ai = Ai[(int64_t)j * ld + i];
+        const int oj = (j * (int)ld + i) * (int)sizeof(R);
+        const R ar = BufLoad<R>::at(fr, oj), ai = BufLoad<R>::at(fi, oj);
         const R lr = ar * rr - ai * ri, lim = ar * ri + ai * rr;
-        Ar[(int64_t)j * ld + i] = lr;
-        Ai[(int64_t)j * ld + i] = lim;
-        for (int c = jj + 1; c < kb; ++c) {
-          const int64_t o = (int64_t)(k + c) * ld + i;
-          const R nr = Ar[o] - (lr * sm.ur[c] - lim * sm.ui[c]);
-          const R ni = Ai[o] - (lr * sm.ui[c] + lim * sm.ur[c]);
-          Ar[o] = nr;
-          Ai[o] = ni;
-          if (c == jj + 1) {
-            const double v = fabs((double)nr) + fabs((double)ni);
-            if (v > best) {
-              best = v;
-              bi = i;
+        BufStore<R>::at(fr, oj, lr);
+        BufStore<R>::at(fi, oj, lim);
+#pragma nounroll
+        for (int h = 0; h < NB; h += 16) {
+          if (h + 16 <= jj + 1 || h >= kb) continue;   // uniform: no live column in this half
+          R xr[16], xi[16];
+          int off[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int c = h + u;
+            off[u] = (c > jj && c < kb) ? ((k + c) * (int)ld + i) * (int)sizeof(R) : kOob;
+            xr[u] = BufLoad<R>::at(fr, off[u]);
+            xi[u] = BufLoad<R>::at(fi, off[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const R pr_ = sm.ur[h + u], pi_ = sm.ui[h + u];
+            xr[u] -= lr * pr_ - lim * pi_;
+            xi[u] -= lr * pi_ + lim * pr_;
+            if (h + u == jj + 1) {
+              const double v = fabs((double)xr[u]) + fabs((double)xi[u]);
+              if (v > best) {
+                best = v;
+                bi = i;
+              }
             }
+            BufStore<R>::at(fr, off[u], xr[u]);
+            BufStore<R>::at(fi, off[u], xi[u]);
           }
         }
       }
@@ -370,23 +512,8 @@ __global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t*
           Ai[o] = sm.Bim[c][i];
         }
       }
-      Wr[c * NB + i] = (in && i >= c) ? sm.Are[c][NB + i] : R(0);
-      Wi[c * NB + i] = (in && i >= c) ? sm.Aim[c][NB + i] : R(0);
     }
     __syncthreads();
-    const int nt = n - k - kb;
-    if (nt > 0) {
-      // U12 = L11^{-1} A12 (in place), then A22 -= L21 U12
-      R* A12r = Ar + (int64_t)(k + kb) * ld + k;
-      R* A12i = Ai + (int64_t)(k + kb) * ld + k;
-      wg_cgemm<R, NB>(kb, nt, Wr, Wi, NB, A12r, A12i, ld, A12r, A12i, ld, false, sm);
-      const R* L21r = Ar + (int64_t)k * ld + k + kb;
-      const R* L21i = Ai + (int64_t)k * ld + k + kb;
-      R* A22r = Ar + (int64_t)(k + kb) * ld + k + kb;
-      R* A22i = Ai + (int64_t)(k + kb) * ld + k + kb;
-      wg_cgemm<R, NB>(nt, nt, L21r, L21i, ld, A12r, A12i, ld, A22r, A22i, ld, true, sm);
-      __syncthreads();
-    }
   }
   if (tid == 0) info[s] = first_zero;
 }
