@@ -5,16 +5,14 @@
 // imaginary plane.  One workgroup (4 wavefronts) factorises one matrix, all
 // matrices in one launch (largest first).  Left-looking, block columns of
 // width NB = 32; for block column J (columns [j0, j0 + 32)):
-//   A. the column block is copied to a row-major scratch X (n x 32);
-//   B. the factored part is applied to it: for the 32-row blocks K < J the
+//   A-C. the factored part is applied to it: for the 32-row blocks K < J the
 //      forward substitution X_K = L_KK^{-1} (X_K - L_{K,<K} X_{<K}), for the
 //      rows below X_rows -= L_{rows,<j0} X_{<j0} -- the same blocked sweep as
 //      the multi-column local solve (64 rows per pass over the factor, the K
 //      range split over the waves, 16x16x4 MFMA products, triangular blocks
 //      as MFMA tile products); each factor entry left of j0 is read once per
-//      block column, and the block column's accumulators never leave the chip
-//      within a pass;
-//   C. X is written back (rows < j0 are U, rows >= j0 the updated panel);
+//      block column; the solved rows (U) also go to a row-major scratch X,
+//      the operand layout of the later passes;
 //   D. panel: unblocked LU of rows [j0, n) with pivot search on |re| + |im|
 //      (lowest row on ties), the search for the next column fused into the
 //      rank-1 update of the current one;
@@ -73,11 +71,17 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
   }
 }
 
-// Step B for block column j0: the 64-row passes over the factored columns.
+// Steps A-C for block column j0 (width kb): 64-row passes over the factored
+// columns.  A pass reads its 64 x kb block of the column from the factor
+// storage (column-major, coalesced through LDS), subtracts the product with the
+// factored part, applies the triangular blocks where the rows are left of j0,
+// and writes the result back to the factor storage and, for rows left of j0
+// (the only rows later passes use as operand), to the row-major scratch X.
 template <typename R, int NB>
-__device__ void apply_factored(SweepSmem<R, NB>& sm, int n, int ld, int j0, __amdgpu_buffer_rsrc_t fr,
-                               __amdgpu_buffer_rsrc_t fi, R* __restrict__ Xr, R* __restrict__ Xi,
-                               __amdgpu_buffer_rsrc_t xrr, __amdgpu_buffer_rsrc_t xir) {
+__device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0, int kb, R* __restrict__ Ar,
+                                    R* __restrict__ Ai, __amdgpu_buffer_rsrc_t fr, __amdgpu_buffer_rsrc_t fi,
+                                    R* __restrict__ Xr, R* __restrict__ Xi, __amdgpu_buffer_rsrc_t xrr,
+                                    __amdgpu_buffer_rsrc_t xir) {
   constexpr int PC = NB, SB = 2 * NB, KU = 8;
   typedef typename Mfma<R>::acc_t acc_t;
   const int wave = threadIdx.x >> 6;
@@ -94,18 +98,20 @@ __device__ void apply_factored(SweepSmem<R, NB>& sm, int n, int ld, int j0, __am
     const int n0 = min(NB, rn), n1 = max(0, rn - NB);
     // prefetch the triangular blocks (first diagonal, coupling, second diagonal)
     R pbr[3][4], pbi[3][4];
+    if (solve0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
-      const int rows[3] = {0, 1, 1}, cols[3] = {0, 0, 1};
-      const int rlim[3] = {n0, n1, n1}, clim[3] = {n0, n0, n1};
-      const bool use[3] = {solve0, solve0, solve1};
+      for (int j = 0; j < 4; ++j) {
+        const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+        const int rows[3] = {0, 1, 1}, cols[3] = {0, 0, 1};
+        const int rlim[3] = {n0, n1, n1}, clim[3] = {n0, n0, n1};
+        const bool use[3] = {true, true, solve1};
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const bool in = use[m] && r < rlim[m] && c < clim[m];
-        const int o = in ? ((r0 + cols[m] * NB + c) * ld + r0 + rows[m] * NB + r) * (int)sizeof(R) : kOob;
-        pbr[m][j] = BufLoad<R>::at(fr, o);
-        pbi[m][j] = BufLoad<R>::at(fi, o);
+        for (int m = 0; m < 3; ++m) {
+          const bool in = use[m] && r < rlim[m] && c < clim[m];
+          const int o = in ? ((r0 + cols[m] * NB + c) * ld + r0 + rows[m] * NB + r) * (int)sizeof(R) : kOob;
+          pbr[m][j] = BufLoad<R>::at(fr, o);
+          pbi[m][j] = BufLoad<R>::at(fi, o);
+        }
       }
     }
     acc_t pre[2][2], pim[2][2];
@@ -126,28 +132,31 @@ __device__ void apply_factored(SweepSmem<R, NB>& sm, int n, int ld, int j0, __am
       __builtin_amdgcn_sched_barrier(0);
       sl.product(pre, pim);
     }
-    // T = X - product; stage the blocks: diagonal inverses as full matrices
-    // (unit lower) for solved blocks, identity otherwise; coupling or zero
+    // T = the block of the column (rows r0.., columns j0..j0+kb) - product
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
-      const int o = r < rn ? (r0 * PC + idx) * (int)sizeof(R) : kOob;
-      sm.Tr[r][c] = BufLoad<R>::at(xrr, o);
-      sm.Ti[r][c] = BufLoad<R>::at(xir, o);
+      const int idx = tid + 256 * j, r = idx % SB, c = idx / SB;
+      const int o = (r < rn && c < kb) ? ((j0 + c) * ld + r0 + r) * (int)sizeof(R) : kOob;
+      sm.Tr[r][c] = BufLoad<R>::at(fr, o);
+      sm.Ti[r][c] = BufLoad<R>::at(fi, o);
     }
+    if (solve0) {
+      // the diagonal inverses as full matrices (unit lower), identity where
+      // the block is right of j0; the coupling block
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+      for (int j = 0; j < 4; ++j) {
+        const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        R vr = pbr[m][j], vi = pbi[m][j];
-        if (m != 1) {
-          const int bn = m == 0 ? n0 : n1;
-          vr = c < r ? vr : (c == r && r < bn ? R(1) : R(0));
-          vi = c < r ? vi : R(0);
+        for (int m = 0; m < 3; ++m) {
+          R vr = pbr[m][j], vi = pbi[m][j];
+          if (m != 1) {
+            const int bn = m == 0 ? n0 : n1;
+            vr = c < r ? vr : (c == r && r < bn ? R(1) : R(0));
+            vi = c < r ? vi : R(0);
+          }
+          sm.Br[m][r][c] = vr;
+          sm.Bi[m][r][c] = vi;
         }
-        sm.Br[m][r][c] = vr;
-        sm.Bi[m][r][c] = vi;
       }
     }
     __syncthreads();
@@ -166,43 +175,66 @@ __device__ void apply_factored(SweepSmem<R, NB>& sm, int n, int ld, int j0, __am
       }
       __syncthreads();
     }
-    // Y0 = M0 T0; T1 -= C Y0; X1 = M1 T1 (M identity and C zero where the
-    // blocks are not yet factored)
-    const int orow = (wave & 1) * 16, ocol = (wave >> 1) * 16 + li;
-    {
-      acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
-      tile_product<R, NB, PC>(sm.Br[0], sm.Bi[0], sm.Tr, sm.Ti, lane, wave, yre, yim);
+    if (solve0) {
+      // Y0 = M0 T0 -> Y; T1 -= C Y0; Y1 = M1 T1 -> rows NB.. of T
+      const int orow = (wave & 1) * 16, ocol = (wave >> 1) * 16 + li;
+      {
+        acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+        tile_product<R, NB, PC>(sm.Br[0], sm.Bi[0], sm.Tr, sm.Ti, lane, wave, yre, yim);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = orow + Mfma<R>::row(lane, q);
-        sm.Yr[r][ocol] = yre[q];
-        sm.Yi[r][ocol] = yim[q];
-        if (r < n0) {
-          Xr[(int64_t)(r0 + r) * PC + ocol] = yre[q];
-          Xi[(int64_t)(r0 + r) * PC + ocol] = yim[q];
+        for (int q = 0; q < 4; ++q) {
+          const int r = orow + Mfma<R>::row(lane, q);
+          sm.Yr[r][ocol] = yre[q];
+          sm.Yi[r][ocol] = yim[q];
+        }
+      }
+      __syncthreads();
+      if (n1 > 0) {
+        acc_t cre = acc_t{0, 0, 0, 0}, cim = acc_t{0, 0, 0, 0};
+        tile_product<R, NB, PC>(sm.Br[1], sm.Bi[1], sm.Yr, sm.Yi, lane, wave, cre, cim);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = orow + Mfma<R>::row(lane, q);
+          sm.Tr[NB + r][ocol] -= cre[q];
+          sm.Ti[NB + r][ocol] -= cim[q];
+        }
+        __syncthreads();
+        acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+        tile_product<R, NB, PC>(sm.Br[2], sm.Bi[2], sm.Tr + NB, sm.Ti + NB, lane, wave, yre, yim);
+        __syncthreads();   // every wave has read T1 before it is overwritten by Y1
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = orow + Mfma<R>::row(lane, q);
+          sm.Tr[NB + r][ocol] = yre[q];
+          sm.Ti[NB + r][ocol] = yim[q];
+        }
+      }
+      // rows r0..r0+32 of the result to Tr as well (from Y)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
+        sm.Tr[r][c] = sm.Yr[r][c];
+        sm.Ti[r][c] = sm.Yi[r][c];
+      }
+      __syncthreads();
+      // rows left of j0 to the row-major scratch (operand of later passes)
+      const int rsolved = min(rn, j0 - r0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
+        if (r < rsolved) {
+          Xr[(int64_t)(r0 + r) * PC + c] = sm.Tr[r][c];
+          Xi[(int64_t)(r0 + r) * PC + c] = sm.Ti[r][c];
         }
       }
     }
-    __syncthreads();
-    if (n1 > 0) {
-      acc_t cre = acc_t{0, 0, 0, 0}, cim = acc_t{0, 0, 0, 0};
-      tile_product<R, NB, PC>(sm.Br[1], sm.Bi[1], sm.Yr, sm.Yi, lane, wave, cre, cim);
+    // the pass's rows back to the factor storage (column-major, coalesced)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = orow + Mfma<R>::row(lane, q);
-        sm.Tr[NB + r][ocol] -= cre[q];
-        sm.Ti[NB + r][ocol] -= cim[q];
-      }
-      __syncthreads();
-      acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
-      tile_product<R, NB, PC>(sm.Br[2], sm.Bi[2], sm.Tr + NB, sm.Ti + NB, lane, wave, yre, yim);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = orow + Mfma<R>::row(lane, q);
-        if (r < n1) {
-          Xr[(int64_t)(r0 + NB + r) * PC + ocol] = yre[q];
-          Xi[(int64_t)(r0 + NB + r) * PC + ocol] = yim[q];
-        }
+    for (int j = 0; j < 8; ++j) {
+      const int idx = tid + 256 * j, r = idx % SB, c = idx / SB;
+      if (r < rn && c < kb) {
+        Ar[(int64_t)(j0 + c) * ld + r0 + r] = sm.Tr[r][c];
+        Ai[(int64_t)(j0 + c) * ld + r0 + r] = sm.Ti[r][c];
       }
     }
     __syncthreads();
@@ -262,49 +294,8 @@ __global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __
 
   for (int k = 0; k < n; k += NB) {
     const int kb = min(NB, n - k);
-    if (k > 0) {
-      // ---- A. block column to the row-major scratch, 64 rows at a time
-      // through LDS (coalesced on both sides)
-      SweepSmem<R, NB>& ts = smu.s;
-      for (int i0 = 0; i0 < n; i0 += 2 * NB) {
-        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
-          const int r = idx % (2 * NB), c = idx / (2 * NB);
-          const bool in = c < kb && i0 + r < n;
-          ts.Tr[r][c] = in ? Ar[(int64_t)(k + c) * ld + i0 + r] : R(0);
-          ts.Ti[r][c] = in ? Ai[(int64_t)(k + c) * ld + i0 + r] : R(0);
-        }
-        __syncthreads();
-        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
-          const int c = idx % NB, r = idx / NB;
-          if (i0 + r < n) {
-            Xr[(int64_t)(i0 + r) * NB + c] = ts.Tr[r][c];
-            Xi[(int64_t)(i0 + r) * NB + c] = ts.Ti[r][c];
-          }
-        }
-        __syncthreads();
-      }
-      // ---- B. apply the factored columns
-      apply_factored<R, NB>(smu.s, n, (int)ld, k, fr, fi, Xr, Xi, xrr, xir);
-      // ---- C. back to the factor storage, through LDS
-      for (int i0 = 0; i0 < n; i0 += 2 * NB) {
-        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
-          const int c = idx % NB, r = idx / NB;
-          if (i0 + r < n) {
-            ts.Tr[r][c] = Xr[(int64_t)(i0 + r) * NB + c];
-            ts.Ti[r][c] = Xi[(int64_t)(i0 + r) * NB + c];
-          }
-        }
-        __syncthreads();
-        for (int idx = tid; idx < 2 * NB * NB; idx += 256) {
-          const int r = idx % (2 * NB), c = idx / (2 * NB);
-          if (c < kb && i0 + r < n) {
-            Ar[(int64_t)(k + c) * ld + i0 + r] = ts.Tr[r][c];
-            Ai[(int64_t)(k + c) * ld + i0 + r] = ts.Ti[r][c];
-          }
-        }
-        __syncthreads();
-      }
-    }
+    // ---- A-C. bring the block column up to date with the factored part
+    if (k > 0) update_block_column<R, NB>(smu.s, n, (int)ld, k, kb, Ar, Ai, fr, fi, Xr, Xi, xrr, xir);
     // ---- 1. panel factorisation; (best, bi): this thread's candidate pivot
     double best = -1.0;
     int bi = 0x7fffffff;
