@@ -324,20 +324,20 @@ __global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __
         }
       if (!(pv > tiny) && first_zero == 0) first_zero = j + 1;
       if (p < j || p >= n) p = j;   // all candidates empty (cannot happen for j < n)
-      if (p != j && tid < kb) {
+      // swap rows j and p of the panel; the pivot row goes to LDS
+      if (tid < kb) {
         const int64_t c = (int64_t)(k + tid) * ld;
-        const R t0 = Ar[c + j], t1 = Ai[c + j];
-        Ar[c + j] = Ar[c + p];
-        Ai[c + j] = Ai[c + p];
-        Ar[c + p] = t0;
-        Ai[c + p] = t1;
+        const R a0 = Ar[c + j], a1 = Ai[c + j], b0 = Ar[c + p], b1 = Ai[c + p];
+        if (p != j) {
+          Ar[c + j] = b0;
+          Ai[c + j] = b1;
+          Ar[c + p] = a0;
+          Ai[c + p] = a1;
+        }
+        sm.ur[tid] = b0;
+        sm.ui[tid] = b1;
       }
       if (tid == 0) sm.piv[jj] = p;
-      __syncthreads();
-      if (tid < kb) {
-        sm.ur[tid] = Ar[(int64_t)(k + tid) * ld + j];
-        sm.ui[tid] = Ai[(int64_t)(k + tid) * ld + j];
-      }
       __syncthreads();
       const R pr = sm.ur[jj], pi = sm.ui[jj];
       const R den = pr * pr + pi * pi;
@@ -348,39 +348,50 @@ __global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __
       // thread at a time: the row's entries of 16 columns are loaded together
       // (branch-free buffer accesses, masked columns out of range), updated
       // in registers and stored
-      for (int i = j + 1 + tid; i < n; i += 256) {
-        const int oj = (j * (int)ld + i) * (int)sizeof(R);
-        const R ar = BufLoad<R>::at(fr, oj), ai = BufLoad<R>::at(fi, oj);
-        const R lr = ar * rr - ai * ri, lim = ar * ri + ai * rr;
-        BufStore<R>::at(fr, oj, lr);
-        BufStore<R>::at(fi, oj, lim);
+      for (int i = j + 1 + tid; i < n; i += 512) {
+        int row[2] = {i, i + 256};
+        int oj[2];
+        R lr[2], lim[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          oj[t] = row[t] < n ? (j * (int)ld + row[t]) * (int)sizeof(R) : kOob;
+          const R ar = BufLoad<R>::at(fr, oj[t]), ai = BufLoad<R>::at(fi, oj[t]);
+          lr[t] = ar * rr - ai * ri;
+          lim[t] = ar * ri + ai * rr;
+          BufStore<R>::at(fr, oj[t], lr[t]);
+          BufStore<R>::at(fi, oj[t], lim[t]);
+        }
 #pragma nounroll
         for (int h = 0; h < NB; h += 16) {
           if (h + 16 <= jj + 1 || h >= kb) continue;   // uniform: no live column in this half
-          R xr[16], xi[16];
-          int off[16];
+          R xr[2][16], xi[2][16];
+          int off[2][16];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int c = h + u;
-            off[u] = (c > jj && c < kb) ? ((k + c) * (int)ld + i) * (int)sizeof(R) : kOob;
-            xr[u] = BufLoad<R>::at(fr, off[u]);
-            xi[u] = BufLoad<R>::at(fi, off[u]);
-          }
+          for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const R pr_ = sm.ur[h + u], pi_ = sm.ui[h + u];
-            xr[u] -= lr * pr_ - lim * pi_;
-            xi[u] -= lr * pi_ + lim * pr_;
-            if (h + u == jj + 1) {
-              const double v = fabs((double)xr[u]) + fabs((double)xi[u]);
-              if (v > best) {
-                best = v;
-                bi = i;
-              }
+            for (int u = 0; u < 16; ++u) {
+              const int c = h + u;
+              off[t][u] = (c > jj && c < kb && row[t] < n) ? ((k + c) * (int)ld + row[t]) * (int)sizeof(R) : kOob;
+              xr[t][u] = BufLoad<R>::at(fr, off[t][u]);
+              xi[t][u] = BufLoad<R>::at(fi, off[t][u]);
             }
-            BufStore<R>::at(fr, off[u], xr[u]);
-            BufStore<R>::at(fi, off[u], xi[u]);
-          }
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+              const R pr_ = sm.ur[h + u], pi_ = sm.ui[h + u];
+              xr[t][u] -= lr[t] * pr_ - lim[t] * pi_;
+              xi[t][u] -= lr[t] * pi_ + lim[t] * pr_;
+              if (h + u == jj + 1 && row[t] < n) {
+                const double v = fabs((double)xr[t][u]) + fabs((double)xi[t][u]);
+                if (v > best || (v == best && row[t] < bi)) {
+                  best = v;
+                  bi = row[t];
+                }
+              }
+              BufStore<R>::at(fr, off[t][u], xr[t][u]);
+              BufStore<R>::at(fi, off[t][u], xi[t][u]);
+            }
         }
       }
     }
@@ -425,22 +436,25 @@ __global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __
       const int np = sm.npairs;
       if (np > 0) {
         const int sr = lane < np ? sm.src[lane] : 0, ds = lane < np ? sm.dst[lane] : 0;
-        for (int c0 = wave * 4; c0 < n; c0 += 16) {
-          R vr[4], vi[4];
-          bool ok[4];
+        // 16 columns per wave in flight; masked lanes and the panel's own
+        // columns read and write out of range (no-ops)
+        for (int c0 = wave * 16; c0 < n; c0 += 64) {
+          R vr[16], vi[16];
+          int od[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 16; ++u) {
             const int c = c0 + u;
-            ok[u] = lane < np && c < n && (c < k || c >= k + kb);
-            vr[u] = ok[u] ? Ar[(int64_t)c * ld + sr] : R(0);
-            vi[u] = ok[u] ? Ai[(int64_t)c * ld + sr] : R(0);
+            const bool ok = lane < np && c < n && (c < k || c >= k + kb);
+            const int os = ok ? (c * (int)ld + sr) * (int)sizeof(R) : kOob;
+            od[u] = ok ? (c * (int)ld + ds) * (int)sizeof(R) : kOob;
+            vr[u] = BufLoad<R>::at(fr, os);
+            vi[u] = BufLoad<R>::at(fi, os);
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (ok[u]) {
-              Ar[(int64_t)(c0 + u) * ld + ds] = vr[u];
-              Ai[(int64_t)(c0 + u) * ld + ds] = vi[u];
-            }
+          for (int u = 0; u < 16; ++u) {
+            BufStore<R>::at(fr, od[u], vr[u]);
+            BufStore<R>::at(fi, od[u], vi[u]);
+          }
         }
       }
     }
