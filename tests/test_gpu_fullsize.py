@@ -1,9 +1,11 @@
-"""Parity at the benchmark's full size (synthetic chamber, r=2, 1,470,500
-unknowns, RCB subdomains, 2 face layers), on outputs the oracle can compute
-piece by piece: every value of the global matrix, the right-hand side, one
-SpMV, and the ORAS application restricted to the unknowns owned by a sample
-of subdomains (each checked against the oracle's own local matrix and sparse
-LU for that subdomain)."""
+"""Parity at the benchmark's full size and launch configuration (synthetic
+chamber, O-grid 22 x 11 x 27 cells, r=2, 1,477,926 unknowns, 3,465
+block-aligned 2 x 2 x 3-cell subdomains, 2 face layers), on outputs the
+oracle can compute piece by piece: every value of the global matrix, the
+right-hand side, one SpMV, the ORAS application (one column, FP64; 32 columns,
+FP32 factors) restricted to the unknowns owned by a sample of subdomains (each
+checked against the oracle's own local matrix and sparse LU for that
+subdomain), and the true residual of a full FP64 solve."""
 import os
 import sys
 
@@ -22,8 +24,9 @@ from paper_1605_04521_amd.api import Layout, Problem
 
 pytestmark = pytest.mark.gpu
 
-N_GRID = int(os.environ.get("MXW_FULL_N", "34"))
-N_SUB = int(os.environ.get("MXW_FULL_NSUB", "2500"))
+N_GRID = int(os.environ.get("MXW_FULL_N", "22"))
+N_Z = int(os.environ.get("MXW_FULL_NZ", "27"))
+N_SUB = tuple(int(q) for q in os.environ.get("MXW_FULL_NSUB", "2x2x3").split("x"))
 
 
 def say(*a):
@@ -48,8 +51,8 @@ def oracle_subdomain(d, part, own, s, layers):
 
 @pytest.fixture(scope="module")
 def full():
-    prob = gen.chamber_problem(n=N_GRID, degree=2, n_sub=N_SUB, overlap=2)
-    say(f"[gpu] full-size chamber n={N_GRID} n_sub={N_SUB}: oracle setup")
+    prob = gen.chamber_problem(n=N_GRID, nz=N_Z, degree=2, n_sub=N_SUB, overlap=2, n_sources=32)
+    say(f"[gpu] full-size chamber n={N_GRID} nz={N_Z} blocks={N_SUB}: oracle setup")
     m = prob.mesh
     d = Discretization(m.xyz, m.tets, prob.eps, m.bfaces, m.bface_kind, prob.k0, prob.degree)
     A = d.global_matrix()
@@ -73,13 +76,7 @@ def test_full_matrix_rhs_spmv(full):
     P.close()
 
 
-def test_full_oras_sampled_subdomains(full):
-    prob, d, A = full
-    say("[gpu] full-size ORAS application, sampled subdomains")
-    P = Problem.from_problem(prob)
-    rng = np.random.default_rng(8)
-    v = rng.standard_normal(d.ndof) + 1j * rng.standard_normal(d.ndof)
-    z = P.apply_prec(torch.from_numpy(v[None]).cuda()).cpu().numpy()[0]
+def check_sampled(prob, d, A, z, v, rng, tol, label):
     own = owners(d, prob.part)
     picks = list(rng.choice(prob.n_sub, size=6, replace=False)) + [0, prob.n_sub - 1]
     lay = Layout.from_problem(prob)
@@ -87,9 +84,50 @@ def test_full_oras_sampled_subdomains(full):
         sub = oracle_subdomain(d, prob.part, own, int(s), prob.overlap)
         dofs, pou = lay.subdomain(int(s))
         assert np.array_equal(dofs, sub.dofs) and np.array_equal(pou, sub.pou), s
-        y = spla.splu(local_matrix(d, sub)).solve(v[sub.dofs])
+        lu = spla.splu(local_matrix(d, sub))
         o = sub.pou == 1
-        err = np.linalg.norm(z[sub.dofs[o]] - y[o]) / np.linalg.norm(y[o])
-        say(f"   subdomain {s}: n_s={len(sub.dofs)} owned={int(o.sum())} rel err {err:.2e}")
-        assert err <= 1e-9, s
+        for c in range(v.shape[0]):
+            y = lu.solve(v[c][sub.dofs])
+            err = np.linalg.norm(z[c][sub.dofs[o]] - y[o]) / np.linalg.norm(y[o])
+            assert err <= tol, (s, c, err)
+        say(f"   {label} subdomain {s}: n_s={len(sub.dofs)} owned={int(o.sum())} last rel err {err:.2e}")
+
+
+def test_full_oras_sampled_subdomains(full):
+    prob, d, A = full
+    say("[gpu] full-size ORAS application (FP64, one column), sampled subdomains")
+    P = Problem.from_problem(prob)
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal((1, d.ndof)) + 1j * rng.standard_normal((1, d.ndof))
+    z = P.apply_prec(torch.from_numpy(v).cuda()).cpu().numpy()
+    check_sampled(prob, d, A, z, v, rng, 1e-9, "fp64")
+    P.close()
+
+
+def test_full_oras_32_columns_mixed(full):
+    """The multi-column kernel in the configuration of the batched benchmark
+    (32 columns, FP32 factors) against the FP64 oracle: FP32 rounding of the
+    factors and of the solve, checked at 1e-4 relative per owned block."""
+    prob, d, A = full
+    say("[gpu] full-size ORAS application (FP32 factors, 32 columns), sampled subdomains")
+    P = Problem.from_problem(prob, precision=B.MXW_MIXED)
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal((32, d.ndof)) + 1j * rng.standard_normal((32, d.ndof))
+    z = P.apply_prec(torch.from_numpy(v).cuda()).cpu().numpy()
+    check_sampled(prob, d, A, z, v[:4], rng, 1e-4, "mixed")
+    P.close()
+
+
+def test_full_solve_true_residual(full):
+    """The benchmark's solve (FP64, one dipole): the true relative residual,
+    recomputed with the oracle's matrix and right-hand side, is below 1e-8."""
+    prob, d, A = full
+    say("[gpu] full-size FGMRES + ORAS solve (FP64, 1 dipole)")
+    P = Problem.from_problem(prob)
+    x, it, rr, st = P.solve(prob.sources[:1])
+    x = x.cpu().numpy()[0]
+    b = d.rhs(prob.sources[0])
+    true_rr = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    say(f"   iterations {it[0]} reported {rr[0]:.3e} true {true_rr:.3e}")
+    assert rr[0] <= 1e-8 and true_rr <= 1.01e-8
     P.close()
