@@ -19,8 +19,6 @@ def hipcc_cmd(out: str, extra=()):
            "-Wno-unused-result", "-o", out]
     cmd += list(extra)
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    # rocBLAS: the plain complex GEMMs of block GMRES (tall basis products)
-    cmd += ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     return cmd
 
 

@@ -1,7 +1,6 @@
 // C ABI of the library: layouts, device problems, ORAS application and the
 // FGMRES driver (Sec. 4-5 of the paper).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -237,7 +236,7 @@ struct KrylovWork {
 // (vector i*p + c of the basis is column c of block i).
 struct BlockWork {
   int p = 0, m = 0, nparts = 0;
-  int64_t ndof = 0, kc = 0;
+  int64_t ndof = 0;
   DevMem mem;
   double2 *H1 = nullptr, *H2 = nullptr, *Hc = nullptr, *part = nullptr, *G = nullptr, *G0 = nullptr, *R1 = nullptr,
           *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *S = nullptr, *T = nullptr, *Rls = nullptr, *E = nullptr,
@@ -245,10 +244,6 @@ struct BlockWork {
   double* est = nullptr;
   int* info = nullptr;   // [0] rank loss, [1] second Gram-Schmidt pass needed
   int64_t reorth = 0;    // second passes in the last solve
-  rocblas_handle h = nullptr;
-  ~BlockWork() {
-    if (h) rocblas_destroy_handle(h);
-  }
 };
 
 struct mxw_problem {
@@ -926,16 +921,7 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
 // ---------------------------------------------------------------------------
 // block FGMRES (one Krylov space shared by the p right-hand sides)
 // ---------------------------------------------------------------------------
-#define BLAS_CHECK(x)                                                         \
-  do {                                                                        \
-    rocblas_status s_ = (x);                                                  \
-    if (s_ != rocblas_status_success) {                                       \
-      set_error(std::string(#x) + ": " + rocblas_status_to_string(s_));       \
-      return MXW_EDEVICE;                                                     \
-    }                                                                         \
-  } while (0)
-
-typedef rocblas_double_complex zc;
+constexpr int kMaxGramParts = 128;   // split-K partial products of a Gram matrix
 
 mxw_status ensure_block(mxw_problem* P, int p, int m) {
   BlockWork& b = P->bw;
@@ -945,9 +931,7 @@ mxw_status ensure_block(mxw_problem* P, int p, int m) {
   b.p = p;
   b.m = m;
   b.ndof = n;
-  // split-K chunk of the Gram products: about 64 partial products
-  b.kc = std::max<int64_t>(2048, ((n + 63) / 64 + 255) / 256 * 256);
-  b.nparts = (int)((n + b.kc - 1) / b.kc);
+  b.nparts = kMaxGramParts;
   const int64_t Q = (int64_t)(m + 1) * p;
   b.H1 = b.mem.alloc<double2>(Q * p);
   b.H2 = b.mem.alloc<double2>(Q * p);
@@ -972,40 +956,25 @@ mxw_status ensure_block(mxw_problem* P, int p, int m) {
     set_error("block Krylov workspace allocation failed");
     return MXW_ENOMEM;
   }
-  if (!b.h) BLAS_CHECK(rocblas_create_handle(&b.h));
   return MXW_OK;
 }
 
 // out (Q x p, column-major) = A^H W, A: Q vectors of length n, W: p vectors,
-// as split-K partial products (rocBLAS) summed in a fixed order
+// as split-K partial products summed in a fixed order
 mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const double2* W, int p, double2* out) {
   BlockWork& b = P->bw;
-  const int64_t n = P->L.ndof, kc = b.kc, nfull = n / kc, tail = n - nfull * kc;
-  const zc one(1.0, 0.0), zero(0.0, 0.0);
-  BLAS_CHECK(rocblas_set_stream(b.h, st));
-  if (nfull > 0)
-    BLAS_CHECK(rocblas_zgemm_strided_batched(b.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, Q, p,
-                                             (rocblas_int)kc, &one, (const zc*)A, (rocblas_int)n, kc, (const zc*)W,
-                                             (rocblas_int)n, kc, &zero, (zc*)b.part, Q, (int64_t)Q * p,
-                                             (rocblas_int)nfull));
-  if (tail > 0)
-    BLAS_CHECK(rocblas_zgemm(b.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, Q, p,
-                             (rocblas_int)tail, &one, (const zc*)(A + nfull * kc), (rocblas_int)n,
-                             (const zc*)(W + nfull * kc), (rocblas_int)n, &zero,
-                             (zc*)(b.part + nfull * (int64_t)Q * p), Q));
-  launch_gram_reduce(st, (int64_t)Q * p, (int)(nfull + (tail > 0)), b.part, out);
+  const int64_t n = P->L.ndof;
+  const int qtiles = (Q + 63) / 64;
+  const int want = std::max(32, std::min(kMaxGramParts, 2048 / qtiles));
+  launch_bgram(st, A, Q, W, p, n, want, b.part);
+  launch_gram_reduce(st, (int64_t)Q * p, bgram_parts(n, want), b.part, out);
   return MXW_OK;
 }
 
 // C (n x p) = alpha A M + beta C; A: K vectors of length n, M: K x p (ld ldm)
 mxw_status tall_gemm(mxw_problem* P, hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p,
                      double alpha, double beta, double2* C) {
-  BlockWork& b = P->bw;
-  const int64_t n = P->L.ndof;
-  const zc za(alpha, 0.0), zb(beta, 0.0);
-  BLAS_CHECK(rocblas_set_stream(b.h, st));
-  BLAS_CHECK(rocblas_zgemm(b.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)n, p, K, &za,
-                           (const zc*)A, (rocblas_int)n, (const zc*)M, ldm, &zb, (zc*)C, (rocblas_int)n));
+  launch_bupdate(st, A, K, M, ldm, p, P->L.ndof, alpha, beta, C, C);
   return MXW_OK;
 }
 

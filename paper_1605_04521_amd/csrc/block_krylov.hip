@@ -1,10 +1,10 @@
 // Block flexible GMRES over one shared Krylov space for all right-hand sides
-// (the block solver of Sec. 5): the small dense kernels.  The products with
-// the tall n x (j+1)p bases are plain complex GEMMs and go to rocBLAS (in
-// api.hip); here live the reductions of their split-K partial products, the
-// Cholesky factor of a Gram matrix (the block QR of a new basis block is a
-// Cholesky QR applied twice), the Householder update of the block Hessenberg
-// least-squares problem, and its back substitution.
+// (the block solver of Sec. 5): the products with the tall n x (j+1)p bases
+// (split-K Gram matrices V^H W and their fixed-order reduction, the updates
+// W -= V H and X += Z Y) on MFMA, the Cholesky factor of a Gram matrix (the
+// block QR of a new basis block is a Cholesky QR applied twice), the
+// Householder update of the block Hessenberg least-squares problem, and its
+// back substitution.
 //
 // Layouts (all complex FP64, column-major):
 //   Hc  (m+1)p x p : new column block of the block Hessenberg matrix
@@ -37,6 +37,140 @@ __global__ void k_gram_reduce(int64_t len, int nparts, const double2* __restrict
 void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H) {
   if (len == 0) return;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, nparts, part, H);
+}
+
+// ---------------------------------------------------------------------------
+// Products with the tall bases (complex FP64 on MFMA, 16x16x4 f64 tiles, four
+// real products per complex tile)
+// ---------------------------------------------------------------------------
+constexpr int kGramChunkStep = 32;   // n entries staged per LDS step
+
+// Split-K Gram partials: part[ch][b*Q + q] = sum over the chunk's entries of
+// conj(V[q][i]) W[b][i], q < Q, b < p <= 32.  Grid (chunks, ceil(Q/64)); the
+// four waves of a workgroup take 16 rows q each; the W and V strips of every
+// 32-entry step are staged in LDS with coalesced loads.
+__global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
+                                               int p, int64_t n, int64_t chunk, double2* __restrict__ part) {
+  typedef Mfma<double>::acc_t acc_t;
+  constexpr int S = kGramChunkStep;
+  __shared__ double2 Vs[64][S + 1];
+  __shared__ double2 Ws[kMaxBlockP][S + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  const int q0 = blockIdx.y * 64;
+  acc_t cre[2], cim[2];
+  for (int t = 0; t < 2; ++t) cre[t] = cim[t] = acc_t{0, 0, 0, 0};
+  for (int64_t is = i0; is < i1; is += S) {
+    for (int idx = tid; idx < 64 * S; idx += 256) {
+      const int r = idx / S, k = idx % S;
+      const int64_t i = is + k;
+      Vs[r][k] = (q0 + r < Q && i < i1) ? V[(int64_t)(q0 + r) * n + i] : make_double2(0.0, 0.0);
+    }
+    for (int idx = tid; idx < kMaxBlockP * S; idx += 256) {
+      const int r = idx / S, k = idx % S;
+      const int64_t i = is + k;
+      Ws[r][k] = (r < p && i < i1) ? W[(int64_t)r * n + i] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < S; k0 += 4) {
+      const double2 a = Vs[wave * 16 + li][k0 + lk];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const double2 b = Ws[t * 16 + li][k0 + lk];
+        // conj(a) b
+        cre[t] = Mfma<double>::op(a.x, b.x, cre[t]);
+        cre[t] = Mfma<double>::op(a.y, b.y, cre[t]);
+        cim[t] = Mfma<double>::op(a.x, b.y, cim[t]);
+        cim[t] = Mfma<double>::op(-a.y, b.x, cim[t]);
+      }
+    }
+    __syncthreads();
+  }
+  double2* out = part + (int64_t)blockIdx.x * Q * p;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = q0 + wave * 16 + Mfma<double>::row(lane, v), b = t * 16 + li;
+      if (q < Q && b < p) out[(int64_t)b * Q + q] = make_double2(cre[t][v], cim[t][v]);
+    }
+}
+
+void launch_bgram(hipStream_t st, const double2* V, int Q, const double2* W, int p, int64_t n, int nchunks,
+                  double2* part) {
+  const int64_t chunk = ((n + nchunks - 1) / nchunks + kGramChunkStep - 1) / kGramChunkStep * kGramChunkStep;
+  const int used = (int)((n + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_bgram, dim3(used, (Q + 63) / 64), dim3(256), 0, st, V, Q, W, p, n, chunk, part);
+}
+
+int bgram_parts(int64_t n, int nchunks) {
+  const int64_t chunk = ((n + nchunks - 1) / nchunks + kGramChunkStep - 1) / kGramChunkStep * kGramChunkStep;
+  return (int)((n + chunk - 1) / chunk);
+}
+
+// out[b][i] = beta C[b][i] + alpha sum_q A[q][i] M[q][b] for b < p <= 32, q < K;
+// M column-major K x p with leading dimension ldm.  Formed as out^T = M^T A^T:
+// each wave owns 32 b x 32 i (lanes run along i, so loads of A and stores of
+// out are coalesced); a workgroup covers 128 entries i.  out may be C.
+__global__ void __launch_bounds__(256) k_bupdate(const double2* __restrict__ A, int K, const double2* __restrict__ M,
+                                                 int ldm, int p, int64_t n, double alpha, double beta,
+                                                 const double2* C, double2* out) {
+  typedef Mfma<double>::acc_t acc_t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int64_t ibase = (int64_t)blockIdx.x * 128 + wave * 32;
+  acc_t dre[2][2], dim[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) dre[t][u] = dim[t][u] = acc_t{0, 0, 0, 0};
+  for (int q0 = 0; q0 < K; q0 += 4) {
+    const int q = q0 + lk;
+    double2 m[2], a[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int b = t * 16 + li;
+      m[t] = (q < K && b < p) ? M[(int64_t)b * ldm + q] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t i = ibase + u * 16 + li;
+      a[u] = (q < K && i < n) ? A[(int64_t)q * n + i] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        dre[t][u] = Mfma<double>::op(m[t].x, a[u].x, dre[t][u]);
+        dre[t][u] = Mfma<double>::op(-m[t].y, a[u].y, dre[t][u]);
+        dim[t][u] = Mfma<double>::op(m[t].x, a[u].y, dim[t][u]);
+        dim[t][u] = Mfma<double>::op(m[t].y, a[u].x, dim[t][u]);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int b = t * 16 + Mfma<double>::row(lane, v);
+        const int64_t i = ibase + u * 16 + li;
+        if (b < p && i < n) {
+          double2 r = make_double2(alpha * dre[t][u][v], alpha * dim[t][u][v]);
+          if (beta != 0.0) {
+            const double2 c = C[(int64_t)b * n + i];
+            r.x += beta * c.x;
+            r.y += beta * c.y;
+          }
+          out[(int64_t)b * n + i] = r;
+        }
+      }
+}
+
+void launch_bupdate(hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p, int64_t n,
+                    double alpha, double beta, const double2* C, double2* out) {
+  hipLaunchKernelGGL(k_bupdate, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, A, K, M, ldm, p, n, alpha,
+                     beta, C, out);
 }
 
 // Cholesky G = R^H R (R upper, p x p) and R^{-1}; optionally S = R Rprev.

@@ -129,6 +129,11 @@ void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const i
 // block GMRES: split-K Gram reduction, Cholesky + inverse of a p x p Gram
 // matrix, block Hessenberg least-squares step and back substitution
 void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H);
+void launch_bgram(hipStream_t st, const double2* V, int Q, const double2* W, int p, int64_t n, int nchunks,
+                  double2* part);
+int bgram_parts(int64_t n, int nchunks);
+void launch_bupdate(hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p, int64_t n,
+                    double alpha, double beta, const double2* C, double2* out);
 void launch_chol(hipStream_t st, int p, const double2* G, double2* R, double2* Rinv, const double2* Rprev,
                  double2* S, int* info);
 void launch_set_e(hipStream_t st, int p, int ldE, const double2* S0, double2* E);
