@@ -324,6 +324,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--krylov", default="pseudo", choices=["pseudo", "block"],
                     help="pseudo-block (one Krylov space per source) or block GMRES (one shared space)")
     ap.add_argument("--graph", action="store_true",
@@ -372,7 +373,8 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         krylov = B.MXW_KRYLOV_BLOCK if args.krylov == "block" else B.MXW_KRYLOV_PSEUDOBLOCK
-        x, it, rr, st = P.solve(prob.sources[:args.nrhs], use_graph=int(args.graph), krylov=krylov)
+        x, it, rr, st = P.solve(prob.sources[:args.nrhs], use_graph=int(args.graph), krylov=krylov,
+                                restart=args.restart)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         phases.append((t1 - t0, t2 - t1))
@@ -419,7 +421,7 @@ def main():
         "vs_baseline": None, "dtype": "f64" if precision == B.MXW_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": wl, "ndof": int(info.ndof), "nnz": int(info.nnz), "n_sub": int(info.n_sub),
                    "max_ns": int(info.max_ns), "nrhs": args.nrhs, "precision": args.precision,
-                   "iterations": iters, "restart": 50, "tol": 1e-8, "graph": bool(args.graph),
+                   "iterations": iters, "restart": args.restart, "tol": 1e-8, "graph": bool(args.graph),
                    "krylov": args.krylov},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "mesh_setup_s": t_mesh,

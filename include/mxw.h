@@ -71,8 +71,10 @@ enum { MXW_SRC_DIPOLE = 0, MXW_SRC_PLANEWAVE = 1 };
  * right-hand side, all operations fused over the columns; BLOCK = one shared
  * block Krylov space (block CGS2 orthogonalisation, Cholesky QR of each new
  * block, Householder block least squares), at most 32 independent, non-zero
- * right-hand sides per solve (MXW_EINVAL otherwise); a block that loses rank
- * before convergence ends the solve with MXW_EBREAKDOWN. */
+ * right-hand sides per solve (MXW_EINVAL otherwise).  A new block that is
+ * numerically rank deficient keeps a floor pivot in its Cholesky QR and the
+ * solve goes on (the true residual at each cycle end decides convergence);
+ * a non-finite residual estimate ends the solve with MXW_EBREAKDOWN. */
 enum { MXW_KRYLOV_PSEUDOBLOCK = 0, MXW_KRYLOV_BLOCK = 1 };
 /* preconditioner variants (Sec. 4): ORAS (default), OAS (no D_s),
  * RAS (Dirichlet transmission: A_s = R_s A R_s^T, with D_s) */

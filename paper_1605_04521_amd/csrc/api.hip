@@ -244,6 +244,7 @@ struct BlockWork {
   double* est = nullptr;
   int* info = nullptr;   // [0] rank loss, [1] second Gram-Schmidt pass needed
   int64_t reorth = 0;    // second passes in the last solve
+  int64_t deflated = 0;  // block steps with a floor pivot in the Cholesky QR
 };
 
 struct mxw_problem {
@@ -964,8 +965,11 @@ mxw_status ensure_block(mxw_problem* P, int p, int m) {
 mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const double2* W, int p, double2* out) {
   BlockWork& b = P->bw;
   const int64_t n = P->L.ndof;
+  // about 2048 workgroups, within the partial-product buffer (sized for
+  // kMaxGramParts parts of the largest Q)
   const int qtiles = (Q + 63) / 64;
-  const int want = std::max(32, std::min(kMaxGramParts, 2048 / qtiles));
+  const int cap = (int)std::min<int64_t>(4096, (int64_t)kMaxGramParts * (b.m + 1) * b.p / Q);
+  const int want = std::max(1, std::min(cap, 2048 / qtiles));
   launch_bgram(st, A, Q, W, p, n, want, b.part);
   launch_gram_reduce(st, (int64_t)Q * p, bgram_parts(n, want), b.part, out);
   return MXW_OK;
@@ -1017,6 +1021,7 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
   HIP_CHECK(hipMemsetAsync(X, 0, sizeof(double2) * n * p, st));
   HIP_CHECK(hipMemcpyAsync(k.Rv, B, sizeof(double2) * n * p, hipMemcpyDeviceToDevice, st));
   b.reorth = 0;
+  b.deflated = 0;
   int steps = 0;
   bool conv = false, breakdown = false;
   while (!conv && steps < opts->max_iters && !breakdown) {
@@ -1066,11 +1071,38 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
       }
       int info = 0;
       std::memcpy(&info, hbuf + p, sizeof(int));
-      if (info) breakdown = true;   // the new block lost rank
+      if (info) {
+        // the new block is numerically rank deficient: the Cholesky QR kept a
+        // floor pivot, the direction carries a negligible weight in the least
+        // squares and the true residual at the cycle end decides
+        ++b.deflated;
+        HIP_CHECK(hipMemsetAsync(b.info, 0, sizeof(int), st));
+      }
+      for (int c = 0; c < p; ++c)
+        if (!std::isfinite(hbuf[c])) breakdown = true;
       if (all || breakdown || steps >= opts->max_iters) break;
     }
-    // X += Z Y; R = B - A X
+    // X += Z Y (only with a finite Y: otherwise the last iterate is kept and
+    // the solve ends with a breakdown); R = B - A X
     launch_bls_solve(st, jd * p, p, m, b.Rls, b.E, b.Y);
+    {
+      std::vector<double2> yh((size_t)m * p * p);
+      HIP_CHECK(hipMemcpyAsync(yh.data(), b.Y, sizeof(double2) * yh.size(), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      bool finite = true;
+      for (int c = 0; c < p && finite; ++c)
+        for (int r = 0; r < jd * p; ++r) {
+          const double2 v = yh[(size_t)c * m * p + r];
+          if (!std::isfinite(v.x) || !std::isfinite(v.y)) {
+            finite = false;
+            break;
+          }
+        }
+      if (!finite) {
+        breakdown = true;
+        break;
+      }
+    }
     TRY(tall_gemm(P, st, k.Z, jd * p, b.Y, m * p, p, 1.0, 1.0, X));
     spmv_dev(P, st, X, k.Rv, B, p, nullptr);
     launch_norm(st, n, k.Rv, n, k.npart, k.beta, p, nullptr);
@@ -1081,6 +1113,7 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
     for (int c = 0; c < p; ++c) {
       relres[c] = hbuf[c] / bnorm[c];
       if (!(relres[c] <= opts->tol)) conv = false;
+      if (!std::isfinite(relres[c])) breakdown = true;
     }
     if (conv) breakdown = false;
   }
@@ -1090,7 +1123,7 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
   }
   if (conv) return MXW_OK;
   if (breakdown) {
-    set_error("block Krylov breakdown (rank-deficient block) before the tolerance");
+    set_error("block Krylov breakdown (non-finite values) before the tolerance");
     return MXW_EBREAKDOWN;
   }
   set_error("max_iters reached before the tolerance");

@@ -46,8 +46,9 @@ void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* 
 constexpr int kGramChunkStep = 32;   // n entries staged per LDS step
 
 // Split-K Gram partials: part[ch][b*Q + q] = sum over the chunk's entries of
-// conj(V[q][i]) W[b][i], q < Q, b < p <= 32.  Grid (chunks, ceil(Q/64)); the
-// four waves of a workgroup take 16 rows q each; the W and V strips of every
+// conj(V[q][i]) W[b][i], q < Q, b < p <= 32.  Grid (ceil(Q/64), chunks), so
+// the workgroups sharing a chunk's strip of W are launched together; the four
+// waves of a workgroup take 16 rows q each; the W and V strips of every
 // 32-entry step are staged in LDS with coalesced loads.
 __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
                                                int p, int64_t n, int64_t chunk, double2* __restrict__ part) {
@@ -56,8 +57,8 @@ __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, in
   __shared__ double2 Vs[64][S + 1];
   __shared__ double2 Ws[kMaxBlockP][S + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-  const int q0 = blockIdx.y * 64;
+  const int64_t i0 = (int64_t)blockIdx.y * chunk, i1 = min(n, i0 + chunk);
+  const int q0 = blockIdx.x * 64;
   acc_t cre[2], cim[2];
   for (int t = 0; t < 2; ++t) cre[t] = cim[t] = acc_t{0, 0, 0, 0};
   for (int64_t is = i0; is < i1; is += S) {
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, in
     }
     __syncthreads();
   }
-  double2* out = part + (int64_t)blockIdx.x * Q * p;
+  double2* out = part + (int64_t)blockIdx.y * Q * p;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -101,7 +102,7 @@ void launch_bgram(hipStream_t st, const double2* V, int Q, const double2* W, int
                   double2* part) {
   const int64_t chunk = ((n + nchunks - 1) / nchunks + kGramChunkStep - 1) / kGramChunkStep * kGramChunkStep;
   const int used = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(k_bgram, dim3(used, (Q + 63) / 64), dim3(256), 0, st, V, Q, W, p, n, chunk, part);
+  hipLaunchKernelGGL(k_bgram, dim3((Q + 63) / 64, used), dim3(256), 0, st, V, Q, W, p, n, chunk, part);
 }
 
 int bgram_parts(int64_t n, int nchunks) {
@@ -174,21 +175,38 @@ void launch_bupdate(hipStream_t st, const double2* A, int K, const double2* M, i
 }
 
 // Cholesky G = R^H R (R upper, p x p) and R^{-1}; optionally S = R Rprev.
-// info[0] = 1 if a pivot is not positive beyond rounding of the largest
-// diagonal entry (the block is rank deficient).
+// info[0] = 1 if a column is zero or a pivot of the scaled Gram matrix is not
+// positive beyond rounding (the block is rank deficient).
 __global__ void __launch_bounds__(256) k_chol(int p, const double2* __restrict__ G, double2* __restrict__ R,
                                               double2* __restrict__ Rinv, const double2* __restrict__ Rprev,
                                               double2* __restrict__ S, int* __restrict__ info) {
   __shared__ double2 A[kMaxBlockP][kMaxBlockP + 1];   // A[row][col], becomes R
   __shared__ double2 Ri[kMaxBlockP][kMaxBlockP + 1];
+  __shared__ double dsc[kMaxBlockP];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < p * p; idx += 256) A[idx % p][idx / p] = G[idx];
-  if (tid == 0) bad = 0;
+  // columns scaled to unit norm first (G -> D^-1 G D^-1, D = diag(G)^1/2):
+  // the Cholesky factor of the scaled Gram matrix is then limited by the
+  // independence of the columns, not by their spread in norm (columns of a
+  // block residual differ by orders of magnitude once some have converged);
+  // R = R~ D and R^-1 = D^-1 R~^-1 restore the scaling
+  // (a column below 1e-14 of the largest norm counts as zero: it is not
+  // scaled up, and its pivot is floored below)
+  double gmax = 0.0;
+  for (int k = 0; k < p; ++k) gmax = fmax(gmax, G[(int64_t)k * p + k].x);
+  if (tid == 0) bad = !(gmax > 0.0) || !isfinite(gmax);
+  if (tid < p) {
+    const double g = G[(int64_t)tid * p + tid].x;
+    dsc[tid] = gmax > 0.0 ? sqrt(fmax(g, 1e-28 * gmax)) : 1.0;
+  }
   __syncthreads();
-  double dmax = 0.0;
-  for (int i = 0; i < p; ++i) dmax = fmax(dmax, A[i][i].x);
-  const double floor_ = 1e-15 * dmax * p;
+  for (int idx = tid; idx < p * p; idx += 256) {
+    const int r = idx % p, c = idx / p;
+    const double sc = 1.0 / (dsc[r] * dsc[c]);
+    A[r][c] = make_double2(G[idx].x * sc, G[idx].y * sc);
+  }
+  __syncthreads();
+  const double floor_ = 1e-15 * p;
   for (int k = 0; k < p; ++k) {
     if (tid == 0) {
       double d = A[k][k].x;
@@ -238,11 +256,21 @@ __global__ void __launch_bounds__(256) k_chol(int p, const double2* __restrict__
     }
   }
   __syncthreads();
+  // undo the column scaling: R = R~ D, R^-1 = D^-1 R~^-1
   for (int idx = tid; idx < p * p; idx += 256) {
     const int r = idx % p, c = idx / p;
-    R[idx] = A[r][c];
-    Rinv[idx] = Ri[r][c];
-    if (S) {
+    R[idx] = make_double2(A[r][c].x * dsc[c], A[r][c].y * dsc[c]);
+    Rinv[idx] = make_double2(Ri[r][c].x / dsc[r], Ri[r][c].y / dsc[r]);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < p * p; idx += 256) {
+    const int r = idx % p, c = idx / p;
+    A[r][c] = make_double2(A[r][c].x * dsc[c], A[r][c].y * dsc[c]);
+  }
+  __syncthreads();
+  if (S) {
+    for (int idx = tid; idx < p * p; idx += 256) {
+      const int r = idx % p, c = idx / p;
       // S = R Rprev (both upper triangular)
       double sr = 0.0, si = 0.0;
       for (int q = r; q <= c; ++q) {
@@ -468,7 +496,9 @@ __global__ void __launch_bounds__(256) k_bls_solve(int jp, int p, int m, const d
       const double2 d = Rls[(int64_t)i * ldR + i];
       const double dd = d.x * d.x + d.y * d.y;
       const double2 yi = Y[(int64_t)tid * ldR + i];
-      const double2 v = make_double2((yi.x * d.x + yi.y * d.y) / dd, (yi.y * d.x - yi.x * d.y) / dd);
+      // a zero diagonal (a direction the block never reached) takes no weight
+      const double2 v = dd > 0.0 ? make_double2((yi.x * d.x + yi.y * d.y) / dd, (yi.y * d.x - yi.x * d.y) / dd)
+                                 : make_double2(0.0, 0.0);
       Y[(int64_t)tid * ldR + i] = v;
       q[tid] = v;
     }
