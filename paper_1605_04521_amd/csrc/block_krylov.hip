@@ -21,22 +21,36 @@ namespace mxw {
 
 constexpr int kMaxBlockP = 32;
 
-// H[idx] = sum over parts of part[t][idx] (+ H2 when accumulating)
-__global__ void k_gram_reduce(int64_t len, int nparts, const double2* __restrict__ part, double2* __restrict__ H) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= len) return;
+// H[idx] = sum over parts of part[t][idx].  A workgroup owns 16 outputs; its
+// 16 groups of 16 threads sum interleaved parts, and the 16 group sums are
+// added in LDS in a fixed order (deterministic for a given part count).
+__global__ void __launch_bounds__(256) k_gram_reduce(int64_t len, int nparts, const double2* __restrict__ part,
+                                                     double2* __restrict__ H) {
+  __shared__ double2 acc[16][17];
+  const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t idx = (int64_t)blockIdx.x * 16 + o;
   double sr = 0.0, si = 0.0;
-  for (int t = 0; t < nparts; ++t) {
-    const double2 a = part[(int64_t)t * len + idx];
-    sr += a.x;
-    si += a.y;
+  if (idx < len)
+    for (int t = g; t < nparts; t += 16) {
+      const double2 a = part[(int64_t)t * len + idx];
+      sr += a.x;
+      si += a.y;
+    }
+  acc[g][o] = make_double2(sr, si);
+  __syncthreads();
+  if (g == 0 && idx < len) {
+    double tr = 0.0, ti = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      tr += acc[q][o].x;
+      ti += acc[q][o].y;
+    }
+    H[idx] = make_double2(tr, ti);
   }
-  H[idx] = make_double2(sr, si);
 }
 
 void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H) {
   if (len == 0) return;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, len, nparts, part, H);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, H);
 }
 
 // ---------------------------------------------------------------------------
@@ -61,18 +75,37 @@ __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, in
   const int q0 = blockIdx.x * 64;
   acc_t cre[2], cim[2];
   for (int t = 0; t < 2; ++t) cre[t] = cim[t] = acc_t{0, 0, 0, 0};
-  for (int64_t is = i0; is < i1; is += S) {
-    for (int idx = tid; idx < 64 * S; idx += 256) {
-      const int r = idx / S, k = idx % S;
+  // the strips of the next step are loaded into registers while the current
+  // step's products run
+  double2 pv[64 * S / 256], pw[kMaxBlockP * S / 256];
+  auto fetch = [&](int64_t is) {
+#pragma unroll
+    for (int u = 0; u < 64 * S / 256; ++u) {
+      const int idx = tid + 256 * u, r = idx / S, k = idx % S;
       const int64_t i = is + k;
-      Vs[r][k] = (q0 + r < Q && i < i1) ? V[(int64_t)(q0 + r) * n + i] : make_double2(0.0, 0.0);
+      pv[u] = (q0 + r < Q && i < i1) ? V[(int64_t)(q0 + r) * n + i] : make_double2(0.0, 0.0);
     }
-    for (int idx = tid; idx < kMaxBlockP * S; idx += 256) {
-      const int r = idx / S, k = idx % S;
+#pragma unroll
+    for (int u = 0; u < kMaxBlockP * S / 256; ++u) {
+      const int idx = tid + 256 * u, r = idx / S, k = idx % S;
       const int64_t i = is + k;
-      Ws[r][k] = (r < p && i < i1) ? W[(int64_t)r * n + i] : make_double2(0.0, 0.0);
+      pw[u] = (r < p && i < i1) ? W[(int64_t)r * n + i] : make_double2(0.0, 0.0);
+    }
+  };
+  if (i0 < i1) fetch(i0);
+  for (int64_t is = i0; is < i1; is += S) {
+#pragma unroll
+    for (int u = 0; u < 64 * S / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Vs[idx / S][idx % S] = pv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kMaxBlockP * S / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Ws[idx / S][idx % S] = pw[u];
     }
     __syncthreads();
+    if (is + S < i1) fetch(is + S);
 #pragma unroll
     for (int k0 = 0; k0 < S; k0 += 4) {
       const double2 a = Vs[wave * 16 + li][k0 + lk];
@@ -125,28 +158,35 @@ __global__ void __launch_bounds__(256) k_bupdate(const double2* __restrict__ A, 
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u) dre[t][u] = dim[t][u] = acc_t{0, 0, 0, 0};
-  for (int q0 = 0; q0 < K; q0 += 4) {
-    const int q = q0 + lk;
-    double2 m[2], a[2];
+  for (int q0 = 0; q0 < K; q0 += 16) {
+    // four 4-wide k steps: every load issued before the products
+    double2 m[4][2], a[4][2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int b = t * 16 + li;
-      m[t] = (q < K && b < p) ? M[(int64_t)b * ldm + q] : make_double2(0.0, 0.0);
-    }
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int q = q0 + 4 * s4 + lk;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t i = ibase + u * 16 + li;
-      a[u] = (q < K && i < n) ? A[(int64_t)q * n + i] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < 2; ++t) {
+        const int b = t * 16 + li;
+        m[s4][t] = (q < K && b < p) ? M[(int64_t)b * ldm + q] : make_double2(0.0, 0.0);
+      }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        dre[t][u] = Mfma<double>::op(m[t].x, a[u].x, dre[t][u]);
-        dre[t][u] = Mfma<double>::op(-m[t].y, a[u].y, dre[t][u]);
-        dim[t][u] = Mfma<double>::op(m[t].x, a[u].y, dim[t][u]);
-        dim[t][u] = Mfma<double>::op(m[t].y, a[u].x, dim[t][u]);
+        const int64_t i = ibase + u * 16 + li;
+        a[s4][u] = (q < K && i < n) ? A[(int64_t)q * n + i] : make_double2(0.0, 0.0);
       }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          dre[t][u] = Mfma<double>::op(m[s4][t].x, a[s4][u].x, dre[t][u]);
+          dre[t][u] = Mfma<double>::op(-m[s4][t].y, a[s4][u].y, dre[t][u]);
+          dim[t][u] = Mfma<double>::op(m[s4][t].x, a[s4][u].y, dim[t][u]);
+          dim[t][u] = Mfma<double>::op(m[s4][t].y, a[s4][u].x, dim[t][u]);
+        }
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -301,22 +341,6 @@ void launch_set_e(hipStream_t st, int p, int ldE, const double2* S0, double2* E)
   hipLaunchKernelGGL(k_set_e, dim3((ldE * p + 255) / 256), dim3(256), 0, st, p, ldE, S0, E);
 }
 
-// Y_out[2p x p] = M[2p x 2p] Y_in[2p x p] for a window of rows in LDS.
-__device__ void window_product(int p, const double2* __restrict__ M, const double2 (*Win)[kMaxBlockP + 1],
-                               double2 (*Wout)[kMaxBlockP + 1]) {
-  const int p2 = 2 * p;
-  for (int idx = threadIdx.x; idx < p2 * p; idx += blockDim.x) {
-    const int r = idx % p2, c = idx / p2;
-    double sr = 0.0, si = 0.0;
-    for (int k = 0; k < p2; ++k) {
-      const double2 a = M[(int64_t)k * p2 + r], b = Win[k][c];
-      sr += a.x * b.x - a.y * b.y;
-      si += a.x * b.y + a.y * b.x;
-    }
-    Wout[r][c] = make_double2(sr, si);
-  }
-}
-
 // Step j of the block Hessenberg least squares (one workgroup):
 //   1. Hc = [H1 + H2 (rows 0..(j+1)p); S (rows (j+1)p..(j+2)p)];
 //   2. apply Q_i^H of the earlier steps to their windows of Hc;
@@ -350,25 +374,48 @@ __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const dou
     Hc[(int64_t)c * ld + r] = v;
   }
   __syncthreads();
-  // 2. earlier transforms, window by window (windows overlap: in order)
+  // 2. earlier transforms, window by window (windows overlap by p rows: in
+  // order).  The lower half of a transformed window is the upper half of the
+  // next one and stays in LDS; Q_i^H is staged in LDS (Qt is free until 3.)
+  for (int idx = tid; idx < p * p; idx += 256) {
+    const int r = idx % p, c = idx / p;
+    A[r][c] = Hc[(int64_t)c * ld + r];
+  }
   for (int i = 0; i < j; ++i) {
-    for (int idx = tid; idx < p2 * p; idx += 256) {
+    for (int idx = tid; idx < p * p; idx += 256) {
+      const int r = idx % p, c = idx / p;
+      A[p + r][c] = Hc[(int64_t)c * ld + (i + 1) * p + r];
+    }
+    for (int idx = tid; idx < p2 * p2; idx += 256) {
       const int r = idx % p2, c = idx / p2;
-      A[r][c] = Hc[(int64_t)c * ld + i * p + r];
+      Qt[r][c] = T[(int64_t)i * p2 * p2 + idx];
     }
     __syncthreads();
-    window_product(p, T + (int64_t)i * p2 * p2, A, B);
+    for (int idx = tid; idx < p2 * p; idx += 256) {
+      const int r = idx % p2, c = idx / p2;
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < p2; ++k) {
+        const double2 a = Qt[r][k], b = A[k][c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      B[r][c] = make_double2(sr, si);
+    }
     __syncthreads();
     for (int idx = tid; idx < p2 * p; idx += 256) {
       const int r = idx % p2, c = idx / p2;
-      Hc[(int64_t)c * ld + i * p + r] = B[r][c];
+      if (r < p)
+        Hc[(int64_t)c * ld + i * p + r] = B[r][c];   // final rows of the column block
+      else
+        A[r - p][c] = B[r][c];                       // carried into the next window
     }
     __syncthreads();
   }
-  // 3. Householder QR of the window at rows jp..(j+2)p
-  for (int idx = tid; idx < p2 * p; idx += 256) {
-    const int r = idx % p2, c = idx / p2;
-    A[r][c] = Hc[(int64_t)c * ld + j * p + r];
+  // 3. Householder QR of the window at rows jp..(j+2)p: the upper half is
+  // the carried (or, for j = 0, the first) block, the lower half S
+  for (int idx = tid; idx < p * p; idx += 256) {
+    const int r = idx % p, c = idx / p;
+    A[p + r][c] = Hc[(int64_t)c * ld + (j + 1) * p + r];
   }
   for (int idx = tid; idx < p2 * p2; idx += 256) {
     const int r = idx % p2, c = idx / p2;
