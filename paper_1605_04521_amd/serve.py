@@ -16,7 +16,7 @@ often on a handful of meshes.  The loop:
   in place (no device allocation);
 * runs every admitted request on its own HIP stream in a worker thread, so the
   kernels of concurrent requests overlap on the device; all right-hand sides of
-  a request are solved together (pseudo-block);
+  a request are solved together (block GMRES, one Krylov space per request);
 * records arrival, start and completion times.
 
 The scheduling core (`Scheduler`) does not touch the GPU, so it is tested on
@@ -140,6 +140,7 @@ class GpuBackend:
     def run(self, req, plan: Plan):
         """Acquire (reuse / re-factorise / create), solve, return to the pool."""
         import torch
+        from . import _lib as B
         from .api import Problem
         base = self.catalogue[req.mesh]
         key = medium_key(req.eps, base.k0)
@@ -155,7 +156,10 @@ class GpuBackend:
             req.reused = "new"
             P = Problem.from_layout(self.layouts[req.mesh], eps=req.eps, k0=base.k0, precision=req.precision)
         try:
-            x, it, rr, st = P.solve(req.sources, allow_notconv=True)
+            # one shared block Krylov space for the request's sources (at most
+            # 32; the block method needs fewer steps than one space per source)
+            krylov = B.MXW_KRYLOV_BLOCK if len(req.sources) <= 32 else B.MXW_KRYLOV_PSEUDOBLOCK
+            x, it, rr, st = P.solve(req.sources, allow_notconv=True, krylov=krylov)
             torch.cuda.current_stream().synchronize()
             req.result, req.iters, req.relres = x.cpu().numpy(), it, rr
         finally:
