@@ -57,19 +57,20 @@ __global__ void __launch_bounds__(256) k_local_solve(const R* __restrict__ F, co
       const R* cr = Ar + b0 + r;
       const R* ci = Ai + b0 + r;
       int c = cg;
-      for (; c + 3 * CG < b0; c += 4 * CG) {
-        const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
-        const R l1r = cr[(int64_t)(c + CG) * ld], l1i = ci[(int64_t)(c + CG) * ld];
-        const R l2r = cr[(int64_t)(c + 2 * CG) * ld], l2i = ci[(int64_t)(c + 2 * CG) * ld];
-        const R l3r = cr[(int64_t)(c + 3 * CG) * ld], l3i = ci[(int64_t)(c + 3 * CG) * ld];
-        s0r += l0r * xr[c] - l0i * xi[c];
-        s0i += l0r * xi[c] + l0i * xr[c];
-        s1r += l1r * xr[c + CG] - l1i * xi[c + CG];
-        s1i += l1r * xi[c + CG] + l1i * xr[c + CG];
-        s0r += l2r * xr[c + 2 * CG] - l2i * xi[c + 2 * CG];
-        s0i += l2r * xi[c + 2 * CG] + l2i * xr[c + 2 * CG];
-        s1r += l3r * xr[c + 3 * CG] - l3i * xi[c + 3 * CG];
-        s1i += l3r * xi[c + 3 * CG] + l3i * xr[c + 3 * CG];
+      for (; c + 7 * CG < b0; c += 8 * CG) {
+        R lr[8], li[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          lr[u] = cr[(int64_t)(c + u * CG) * ld];
+          li[u] = ci[(int64_t)(c + u * CG) * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          s0r += lr[u] * xr[c + u * CG] - li[u] * xi[c + u * CG];
+          s0i += lr[u] * xi[c + u * CG] + li[u] * xr[c + u * CG];
+          s1r += lr[u + 1] * xr[c + (u + 1) * CG] - li[u + 1] * xi[c + (u + 1) * CG];
+          s1i += lr[u + 1] * xi[c + (u + 1) * CG] + li[u + 1] * xr[c + (u + 1) * CG];
+        }
       }
       for (; c < b0; c += CG) {
         const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
@@ -122,19 +123,20 @@ __global__ void __launch_bounds__(256) k_local_solve(const R* __restrict__ F, co
       const R* cr = Ar + b0 + r;
       const R* ci = Ai + b0 + r;
       int c = b0 + bn + cg;
-      for (; c + 3 * CG < n; c += 4 * CG) {
-        const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
-        const R l1r = cr[(int64_t)(c + CG) * ld], l1i = ci[(int64_t)(c + CG) * ld];
-        const R l2r = cr[(int64_t)(c + 2 * CG) * ld], l2i = ci[(int64_t)(c + 2 * CG) * ld];
-        const R l3r = cr[(int64_t)(c + 3 * CG) * ld], l3i = ci[(int64_t)(c + 3 * CG) * ld];
-        s0r += l0r * xr[c] - l0i * xi[c];
-        s0i += l0r * xi[c] + l0i * xr[c];
-        s1r += l1r * xr[c + CG] - l1i * xi[c + CG];
-        s1i += l1r * xi[c + CG] + l1i * xr[c + CG];
-        s0r += l2r * xr[c + 2 * CG] - l2i * xi[c + 2 * CG];
-        s0i += l2r * xi[c + 2 * CG] + l2i * xr[c + 2 * CG];
-        s1r += l3r * xr[c + 3 * CG] - l3i * xi[c + 3 * CG];
-        s1i += l3r * xi[c + 3 * CG] + l3i * xr[c + 3 * CG];
+      for (; c + 7 * CG < n; c += 8 * CG) {
+        R lr[8], li[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          lr[u] = cr[(int64_t)(c + u * CG) * ld];
+          li[u] = ci[(int64_t)(c + u * CG) * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          s0r += lr[u] * xr[c + u * CG] - li[u] * xi[c + u * CG];
+          s0i += lr[u] * xi[c + u * CG] + li[u] * xr[c + u * CG];
+          s1r += lr[u + 1] * xr[c + (u + 1) * CG] - li[u + 1] * xi[c + (u + 1) * CG];
+          s1i += lr[u + 1] * xi[c + (u + 1) * CG] + li[u + 1] * xr[c + (u + 1) * CG];
+        }
       }
       for (; c < n; c += CG) {
         const R l0r = cr[(int64_t)c * ld], l0i = ci[(int64_t)c * ld];
