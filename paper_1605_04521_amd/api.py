@@ -26,9 +26,12 @@ class Layout:
         return cls(B.Desc.from_problem(prob, **kw))
 
     def __del__(self):
-        if getattr(self, "h", None) is not None and self.h.value:
-            B.lib().mxw_layout_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None) is not None and self.h.value:
+                B.lib().mxw_layout_destroy(self.h)
+                self.h = None
+        except (TypeError, AttributeError):
+            pass   # interpreter shutdown: the module's globals are already gone
 
     def info(self) -> B.LayoutInfo:
         i = B.LayoutInfo()
@@ -123,9 +126,10 @@ class Problem:
         return cls(B.Desc.from_problem(prob, precision, variant), **kw)
 
     def __del__(self):
-        if getattr(self, "h", None) is not None and self.h.value:
-            B.lib().mxw_problem_destroy(self.h)
-            self.h = None
+        try:
+            self.close()
+        except (TypeError, AttributeError):
+            pass   # interpreter shutdown: the module's globals are already gone
 
     def info(self) -> B.LayoutInfo:
         i = B.LayoutInfo()
