@@ -327,6 +327,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--variant", default="oras", choices=["oras", "oas", "ras"],
+                    help="Schwarz variant: Robin (ORAS), no partition of unity (OAS), Dirichlet (RAS)")
     ap.add_argument("--krylov", default="pseudo", choices=["pseudo", "block"],
                     help="pseudo-block (one Krylov space per source) or block GMRES (one shared space)")
     ap.add_argument("--graph", action="store_true",
@@ -369,7 +371,8 @@ def main():
     def one_step():
         t0 = time.perf_counter()
         if "P" not in holder:
-            holder["P"] = Problem.from_layout(lay, eps=prob.eps, k0=prob.k0, precision=precision)
+            variant = {"oras": B.MXW_PREC_ORAS, "oas": B.MXW_PREC_OAS, "ras": B.MXW_PREC_RAS}[args.variant]
+            holder["P"] = Problem.from_layout(lay, eps=prob.eps, k0=prob.k0, precision=precision, variant=variant)
         else:
             holder["P"].set_medium(prob.eps, prob.k0)
         P = holder["P"]
@@ -430,7 +433,7 @@ def main():
         "vs_baseline": None, "dtype": "f64" if precision == B.MXW_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": wl, "ndof": int(info.ndof), "nnz": int(info.nnz), "n_sub": int(info.n_sub),
                    "max_ns": int(info.max_ns), "nrhs": args.nrhs, "sources_per_step": nsources, "precision": args.precision,
-                   "iterations": iters, "restart": args.restart, "tol": 1e-8, "graph": bool(args.graph),
+                   "iterations": iters, "restart": args.restart, "tol": 1e-8, "variant": args.variant, "graph": bool(args.graph),
                    "krylov": args.krylov},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "mesh_setup_s": t_mesh,

@@ -439,7 +439,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
     return MXW_ENOMEM;
   }
   k.xbuf = nullptr;
-  if (nrhs >= 2 && P->variant == MXW_PREC_ORAS) {
+  if (nrhs >= 2 && P->variant != MXW_PREC_OAS) {
     const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
     k.xbuf = k.mem.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() * (P->mixed ? 4 : 8));
     if (!k.xbuf) {
@@ -458,7 +458,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
 // z = M^{-1} v for ncol columns (device, stride ndof)
 void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vstride, double2* z, int64_t zstride,
                     int ncol, const int* active, double2* ys, void* xbuf = nullptr) {
-  if (xbuf && ncol >= 2 && P->variant == MXW_PREC_ORAS) {
+  if (xbuf && ncol >= 2 && P->variant != MXW_PREC_OAS) {
     ScopedKernelTimer tm("local_solve_multi");
     LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
                      P->order};
@@ -507,7 +507,11 @@ mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor) {
                        L.basis.nfloc};
   {
     ScopedTimer tm(st, "local_assemble");
-    launch_assemble_local<R>(st, la, (R*)P->F);
+    if (P->variant == MXW_PREC_RAS)
+      launch_local_from_csr<R>(st, L.n_sub, (R*)P->F, P->foff, P->nsz, P->lds, P->poff, P->sub_dofs, P->rowptr,
+                               P->cols, P->vals);
+    else
+      launch_assemble_local<R>(st, la, (R*)P->F);
   }
   HIP_CHECK(hipGetLastError());
   if (factor) {
@@ -809,8 +813,8 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
     set_error("unknown precision");
     return MXW_EINVAL;
   }
-  if (variant != MXW_PREC_ORAS && variant != MXW_PREC_OAS) {
-    set_error("preconditioner variant not available (ORAS and OAS are)");
+  if (variant != MXW_PREC_ORAS && variant != MXW_PREC_OAS && variant != MXW_PREC_RAS) {
+    set_error("unknown preconditioner variant");
     return MXW_EINVAL;
   }
   if (!std::isfinite(k0) || k0 < 0) {
@@ -1344,7 +1348,7 @@ mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double*
   double2* ys = nullptr;
   void* xbuf = nullptr;
   if (prob->variant == MXW_PREC_OAS) HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
-  if (prob->variant == MXW_PREC_ORAS && nrhs >= 2) {
+  if (prob->variant != MXW_PREC_OAS && nrhs >= 2) {
     const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
     HIP_CHECK(hipMallocAsync(&xbuf, (size_t)nchunk * 2 * prob->L.sum_ns * multi_chunk_cols() * (prob->mixed ? 4 : 8), st));
   }

@@ -453,6 +453,61 @@ void launch_assemble_rows(hipStream_t st, const AssembleArgs& a) {
                      a.ft_dofs, a.nfloc, a.BF, a.vals);
 }
 
+// Dirichlet transmission (RAS, Sec. 4): A_s = R_s A R_s^T, the principal
+// submatrix of the assembled global matrix on the subdomain's unknowns.  One
+// workgroup per subdomain: the dense matrix is cleared, then each local row
+// scans its global CSR row and places the entries whose column belongs to the
+// subdomain (binary search in the sorted unknown list).
+template <typename R>
+__global__ void __launch_bounds__(256) k_local_from_csr(R* __restrict__ F, const int64_t* __restrict__ foff,
+                                                        const int* __restrict__ nsz, const int* __restrict__ lds,
+                                                        const int64_t* __restrict__ poff,
+                                                        const int* __restrict__ sub_dofs,
+                                                        const int64_t* __restrict__ rowptr,
+                                                        const int* __restrict__ cols,
+                                                        const double2* __restrict__ vals) {
+  const int s = blockIdx.x;
+  const int n = nsz[s], ld = lds[s];
+  R* re = F + foff[s];
+  R* im = re + (int64_t)ld * n;
+  const int64_t tot = 2 * (int64_t)ld * n;
+  for (int64_t q = threadIdx.x; q < tot; q += blockDim.x) re[q] = R(0);
+  __syncthreads();
+  const int* D = sub_dofs + poff[s];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int g = D[i];
+    for (int64_t e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+      const int c = cols[e];
+      int lo = 0, hi = n;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (D[mid] < c)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < n && D[lo] == c) {
+        const double2 a = vals[e];
+        re[(int64_t)lo * ld + i] = (R)a.x;
+        im[(int64_t)lo * ld + i] = (R)a.y;
+      }
+    }
+  }
+}
+
+template <typename R>
+void launch_local_from_csr(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds,
+                           const int64_t* poff, const int* sub_dofs, const int64_t* rowptr, const int* cols,
+                           const double2* vals) {
+  if (n_sub == 0) return;
+  hipLaunchKernelGGL(k_local_from_csr<R>, dim3(n_sub), dim3(256), 0, st, F, foff, nsz, lds, poff, sub_dofs, rowptr,
+                     cols, vals);
+}
+template void launch_local_from_csr<double>(hipStream_t, int, double*, const int64_t*, const int*, const int*,
+                                            const int64_t*, const int*, const int64_t*, const int*, const double2*);
+template void launch_local_from_csr<float>(hipStream_t, int, float*, const int64_t*, const int*, const int*,
+                                           const int64_t*, const int*, const int64_t*, const int*, const double2*);
+
 template <typename R>
 void launch_assemble_local(hipStream_t st, const LocalAssembleArgs& a, R* F) {
   if (a.n_sub == 0) return;

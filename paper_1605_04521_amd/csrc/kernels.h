@@ -70,6 +70,10 @@ struct LocalAssembleArgs {
 };
 template <typename R>
 void launch_assemble_local(hipStream_t st, const LocalAssembleArgs& a, R* F);
+template <typename R>
+void launch_local_from_csr(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds,
+                           const int64_t* poff, const int* sub_dofs, const int64_t* rowptr, const int* cols,
+                           const double2* vals);
 
 void launch_rhs_dipole(hipStream_t st, const double* xyz, const int* tets, const int* tet_dofs, const Term* phi,
                        int nloc, int64_t t, const double lam[4], const double pr[3], const double pi[3],
