@@ -118,7 +118,10 @@ def local_matrix(disc: Discretization, sub: Subdomain, dirichlet: bool = False):
 
 class ORAS:
     """z = sum_s R_s^T D_s A_s^{-1} R_s v (variant='oras'); 'oas' drops D_s;
-    'ras' uses A_s = R_s A R_s^T (Dirichlet transmission) with D_s."""
+    'ras' uses A_s = R_s A R_s^T (Dirichlet transmission) with D_s;
+    'oras_mult' keeps the Robin A_s and takes the partition of unity by
+    multiplicity, D_s = diag(1 / number of subdomains containing the unknown)
+    (Sec. 4 allows any D_s with sum_s R_s^T D_s R_s = I)."""
 
     def __init__(self, disc: Discretization, part, n_sub: int, layers: int, variant: str = "oras",
                  A=None):
@@ -131,13 +134,24 @@ class ORAS:
             else:
                 sub.A = local_matrix(disc, sub)
             sub.lu = spla.splu(sub.A)
+        if variant == "oras_mult":
+            mult = np.zeros(disc.ndof)
+            for sub in self.subs:
+                mult[sub.dofs] += 1.0
+            for sub in self.subs:
+                sub.weight = 1.0 / mult[sub.dofs]
+
+    def weights(self, sub):
+        """The diagonal of D_s."""
+        if self.variant == "oas":
+            return np.ones(len(sub.dofs))
+        if self.variant == "oras_mult":
+            return sub.weight
+        return sub.pou.astype(np.float64)
 
     def apply(self, v):
         z = np.zeros(len(v), dtype=np.complex128)
         for sub in self.subs:
             y = sub.lu.solve(np.asarray(v[sub.dofs], dtype=np.complex128))
-            if self.variant == "oas":
-                z[sub.dofs] += y
-            else:
-                z[sub.dofs] += sub.pou * y
+            z[sub.dofs] += self.weights(sub) * y
         return z

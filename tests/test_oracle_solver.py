@@ -216,3 +216,42 @@ def test_block_fgmres():
     X, steps, rel, ok = block_fgmres(lambda V: A @ V, lambda V: V, B, tol=1e-10, restart=3)
     assert ok and np.all(rel <= 1e-10)
     assert np.linalg.norm(A @ X - B) <= 1e-9 * np.linalg.norm(B)
+
+
+@pytest.mark.parametrize("variant", ["oras", "ras", "oras_mult"])
+def test_variants_are_partitions_of_unity(variant):
+    """sum_s R_s^T D_s R_s = I for the Boolean (ORAS, RAS) and the
+    multiplicity (ORAS_MULT) weights: the preconditioner maps a vector that
+    every local solve reproduces exactly (A_s = I) to itself.  Checked with
+    the weights the oracle's application uses."""
+    prob = gen.chamber_problem(n=4, degree=2, n_sub=5, overlap=2)
+    s = OracleSolver.from_problem(prob, variant)
+    acc = np.zeros(s.ndof)
+    for sub in s.prec.subs:
+        acc[sub.dofs] += s.prec.weights(sub)
+    assert np.allclose(acc, 1.0, rtol=0, atol=1e-15)
+    if variant == "oras_mult":
+        w = np.concatenate([s.prec.weights(sub) for sub in s.prec.subs])
+        assert w.min() < 1.0   # some unknowns lie in several subdomains
+
+
+@pytest.mark.parametrize("variant", ["ras", "oras_mult"])
+def test_variant_one_subdomain_is_a_direct_solve(variant):
+    """One subdomain: R_1 = I, D_1 = I and A_1 = A for every variant (no
+    interface), so one iteration solves the system."""
+    prob = gen.cube_planewave_problem(n=3, degree=2)
+    prob.part[:] = 0
+    prob.n_sub = 1
+    s = OracleSolver.from_problem(prob, variant)
+    x, it, rr, ok = s.solve(s.rhs(prob.sources[0]))
+    assert ok and it == 1
+
+
+def test_ras_local_matrix_is_principal_submatrix():
+    """RAS: A_s = R_s A R_s^T, i.e. the global matrix restricted to the
+    subdomain's unknowns, entry by entry (checked against the dense A)."""
+    prob = gen.chamber_problem(n=3, degree=1, n_sub=3, overlap=1)
+    s = OracleSolver.from_problem(prob, "ras")
+    Ad = s.A.toarray()
+    for sub in s.prec.subs:
+        assert np.array_equal(sub.A.toarray(), Ad[np.ix_(sub.dofs, sub.dofs)])
