@@ -327,8 +327,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--variant", default="oras", choices=["oras", "oas", "ras"],
-                    help="Schwarz variant: Robin (ORAS), no partition of unity (OAS), Dirichlet (RAS)")
+    ap.add_argument("--variant", default="oras", choices=["oras", "oas", "ras", "oras_mult"],
+                    help="Schwarz variant: Robin (ORAS), no partition of unity (OAS), Dirichlet (RAS), "
+                         "Robin with the multiplicity partition of unity (ORAS_MULT)")
     ap.add_argument("--krylov", default="pseudo", choices=["pseudo", "block"],
                     help="pseudo-block (one Krylov space per source) or block GMRES (one shared space)")
     ap.add_argument("--graph", action="store_true",
@@ -371,7 +372,8 @@ def main():
     def one_step():
         t0 = time.perf_counter()
         if "P" not in holder:
-            variant = {"oras": B.MXW_PREC_ORAS, "oas": B.MXW_PREC_OAS, "ras": B.MXW_PREC_RAS}[args.variant]
+            variant = {"oras": B.MXW_PREC_ORAS, "oas": B.MXW_PREC_OAS, "ras": B.MXW_PREC_RAS,
+                       "oras_mult": B.MXW_PREC_ORAS_MULT}[args.variant]
             holder["P"] = Problem.from_layout(lay, eps=prob.eps, k0=prob.k0, precision=precision, variant=variant)
         else:
             holder["P"].set_medium(prob.eps, prob.k0)
