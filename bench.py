@@ -332,6 +332,12 @@ def main():
                          "Robin with the multiplicity partition of unity (ORAS_MULT)")
     ap.add_argument("--krylov", default="pseudo", choices=["pseudo", "block"],
                     help="pseudo-block (one Krylov space per source) or block GMRES (one shared space)")
+    ap.add_argument("--sequence", action="store_true",
+                    help="slowly varying media: step i scales eps by 1 + 0.01 i (an imaging-loop sequence)")
+    ap.add_argument("--recycle", type=int, default=0,
+                    help="solve with GCRO-DR, recycling a space of this many vectors from system to system")
+    ap.add_argument("--tune", action="store_true",
+                    help="after the warm-up, time the tile choices on the problem and keep the fastest")
     ap.add_argument("--graph", action="store_true",
                     help="replay each Arnoldi step as a captured HIP graph (kernel timers are off inside graphs)")
     args = ap.parse_args()
@@ -371,12 +377,16 @@ def main():
 
     def one_step():
         t0 = time.perf_counter()
+        eps = prob.eps
+        if args.sequence:
+            eps = prob.eps * (1.0 + 0.01 * holder.get("seq", 0))
+            holder["seq"] = holder.get("seq", 0) + 1
         if "P" not in holder:
             variant = {"oras": B.MXW_PREC_ORAS, "oas": B.MXW_PREC_OAS, "ras": B.MXW_PREC_RAS,
                        "oras_mult": B.MXW_PREC_ORAS_MULT}[args.variant]
-            holder["P"] = Problem.from_layout(lay, eps=prob.eps, k0=prob.k0, precision=precision, variant=variant)
+            holder["P"] = Problem.from_layout(lay, eps=eps, k0=prob.k0, precision=precision, variant=variant)
         else:
-            holder["P"].set_medium(prob.eps, prob.k0)
+            holder["P"].set_medium(eps, prob.k0)
         P = holder["P"]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -384,8 +394,12 @@ def main():
         # all sources of the step, nrhs at a time (one block each)
         its, rrs = [], []
         for c0 in range(0, nsources, args.nrhs):
-            x, it, rr, st = P.solve(prob.sources[c0:c0 + args.nrhs], use_graph=int(args.graph), krylov=krylov,
-                                    restart=args.restart)
+            if args.recycle:
+                b = P.rhs(prob.sources[c0:c0 + args.nrhs])
+                x, it, rr, st = P.solve_recycle(b, k=args.recycle, restart=args.restart)
+            else:
+                x, it, rr, st = P.solve(prob.sources[c0:c0 + args.nrhs], use_graph=int(args.graph),
+                                        krylov=krylov, restart=args.restart)
             its.append(it)
             rrs.append(rr)
         it, rr = np.concatenate(its), np.concatenate(rrs)
@@ -401,6 +415,13 @@ def main():
         it, rr = one_step()
         log(f"[bench] warmup {w}: iters={it.tolist()} relres={rr.tolist()} {time.perf_counter()-t0:.2f}s")
         t0 = time.perf_counter()
+
+    tiles = None
+    if args.tune:
+        if "P" not in holder:
+            one_step()  # untimed: creates and factors the problem
+        tiles = holder["P"].tune(args.nrhs)
+        log(f"[bench] tuned tiles {tiles}")
 
     timing(not args.no_kernel_timing)
     reset_timing()
@@ -436,13 +457,15 @@ def main():
         "config": {"workload": wl, "ndof": int(info.ndof), "nnz": int(info.nnz), "n_sub": int(info.n_sub),
                    "max_ns": int(info.max_ns), "nrhs": args.nrhs, "sources_per_step": nsources, "precision": args.precision,
                    "iterations": iters, "restart": args.restart, "tol": 1e-8, "variant": args.variant, "graph": bool(args.graph),
-                   "krylov": args.krylov},
+                   "krylov": "gcro-dr k=%d" % args.recycle if args.recycle else args.krylov,
+                   "medium": "scaled by 1 + 0.01 i at step i" if args.sequence else "fixed"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "mesh_setup_s": t_mesh,
         "phase_s": {"assemble_factor": float(np.median([p[0] for p in phases[-args.steps:]])),
                     "solve": float(np.median([p[1] for p in phases[-args.steps:]]))},
         "roofline": roof,
         "kernels": kern,
+        "tiles": tiles,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample (CPU)")

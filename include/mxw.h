@@ -76,9 +76,12 @@ enum { MXW_SRC_DIPOLE = 0, MXW_SRC_PLANEWAVE = 1 };
  * solve goes on (the true residual at each cycle end decides convergence);
  * a non-finite residual estimate ends the solve with MXW_EBREAKDOWN. */
 enum { MXW_KRYLOV_PSEUDOBLOCK = 0, MXW_KRYLOV_BLOCK = 1 };
-/* preconditioner variants (Sec. 4): ORAS (default), OAS (no D_s),
- * RAS (Dirichlet transmission: A_s = R_s A R_s^T, with D_s) */
-enum { MXW_PREC_ORAS = 0, MXW_PREC_OAS = 1, MXW_PREC_RAS = 2 };
+/* preconditioner variants (Sec. 4): ORAS (default: Robin transmission,
+ * Boolean partition of unity), OAS (no D_s), RAS (Dirichlet transmission:
+ * A_s = R_s A R_s^T, Boolean D_s), ORAS_MULT (Robin transmission, partition
+ * of unity by multiplicity: D_s = diag(1 / number of subdomains containing
+ * the unknown)) */
+enum { MXW_PREC_ORAS = 0, MXW_PREC_OAS = 1, MXW_PREC_RAS = 2, MXW_PREC_ORAS_MULT = 3 };
 
 typedef struct {
   int64_t n_vertices;
@@ -225,6 +228,67 @@ mxw_status mxw_solve(mxw_problem* prob, int32_t nrhs, const mxw_source* src,
 mxw_status mxw_solve_rhs(mxw_problem* prob, int32_t nrhs, const double* b_dev,
                          const mxw_solve_opts* opts, void* stream, double* x_dev,
                          int32_t* iters_out, double* relres_out);
+
+/* Krylov subspace recycling (Sec. 6: GCRO-DR, the method of Parks, de Sturler
+ * et al., 2006, proposed there for the slowly varying systems of the imaging
+ * loop).  Solves A x_j = b_j for the nrhs right-hand sides one after another
+ * (device complex128 [nrhs][ndof] in b_dev and x_dev), each by GCRO-DR on the
+ * right-preconditioned operator A M^{-1} (x0 = 0), carrying a recycled space
+ * of k vectors held by the problem from one system to the next:
+ *  - a space made for another operator (after mxw_problem_set_medium or a
+ *    new factorisation) is first carried over: C = A M^{-1} U recomputed and
+ *    orthonormalised (k preconditioner applications and products);
+ *  - every cycle removes the residual's part in range(C), runs restart - k
+ *    Arnoldi steps of (I - C C^H) A M^{-1} (restart steps while no space
+ *    exists yet), updates x, and replaces the space by the k harmonic Ritz
+ *    vectors of smallest harmonic Ritz value of the cycle's search space.
+ * opts->restart = vectors per cycle (k < restart <= 64), 1 <= k <= 32,
+ * opts->tol, opts->max_iters as for mxw_solve; opts->krylov and use_graph
+ * are ignored.  iters_out counts Arnoldi steps.  A different k or restart
+ * than the previous call drops the space.  Device memory held by the
+ * problem: (2 restart + 5 k + 3) ndof complex128 and small matrices.
+ * MXW_ENOTCONV / MXW_EBREAKDOWN as for mxw_solve; MXW_EINVAL for bad
+ * options or an unfactorised problem. */
+mxw_status mxw_solve_recycle(mxw_problem* prob, int32_t nrhs, const double* b_dev,
+                             const mxw_solve_opts* opts, int32_t k, void* stream, double* x_dev,
+                             int32_t* iters_out, double* relres_out);
+/* Forgets the recycled space (the next recycling solve starts as GMRES). */
+mxw_status mxw_recycle_reset(mxw_problem* prob);
+/* The recycled space: dim receives its dimension; any of U, Ubar = M^{-1} U
+ * and C = A Ubar (C^H C = I) that is not NULL receives dim device vectors
+ * [dim][ndof] complex128 (caller-allocated).  Synchronises the stream. */
+mxw_status mxw_recycle_export(mxw_problem* prob, int32_t* dim, double* U_dev, double* Ubar_dev,
+                              double* C_dev, void* stream);
+/* Counters of the problem's recycling: spaces carried to a new operator,
+ * deflated restarts, and restarts whose small eigenproblem failed (the space
+ * is then dropped and the solve goes on without it).  NULL outputs skipped. */
+mxw_status mxw_recycle_stats(const mxw_problem* prob, int64_t* refreshes, int64_t* deflations,
+                             int64_t* failures);
+
+/* Tile choices of the hot kernels, measured on one problem. */
+typedef struct {
+  int32_t spmv_group;         /* lanes per matrix row chosen for the SpMV */
+  int32_t multi_ku;           /* k slice width chosen for the multi-column local solve */
+  double spmv_ms[4];          /* time per SpMV launch with 4, 8, 16, 32 lanes per row */
+  double multi_ms[2];         /* time per multi-column local solve with 4-, 8-wide k
+                                 slices (0 where not measured) */
+} mxw_tuning;
+
+/* Autotuner (launch mechanics; not a passage of the paper): times the SpMV
+ * on nrhs columns with 4, 8, 16 and 32 lanes per row and, for nrhs >= 2, a
+ * Boolean partition of unity (ORAS, RAS) and a factorised problem, the
+ * multi-column local solve with 4- and 8-wide k slices, on this problem's own
+ * operator and factors; later calls on the problem use the fastest of each.
+ * Results do not depend on the choice beyond rounding.  Allocates temporary
+ * device buffers (2 nrhs ndof complex128, plus the multi-column scratch) and
+ * synchronises the stream.  out may be NULL.  MXW_EINVAL for nrhs outside
+ * 1..4096. */
+mxw_status mxw_problem_tune(mxw_problem* prob, int32_t nrhs, void* stream, mxw_tuning* out);
+
+/* Sets the tile choices by hand (for instance those a previous
+ * mxw_problem_tune call picked): spmv_group in {4, 8, 16, 32}, multi_ku in
+ * {4, 8}; 0 leaves a choice unchanged.  MXW_EINVAL for other values. */
+mxw_status mxw_problem_set_tiles(mxw_problem* prob, int32_t spmv_group, int32_t multi_ku);
 
 /* Residual estimates |g_{j+1}| / ||b|| of every Arnoldi step of column col
  * in the last solve on this problem (host array; len receives the count,

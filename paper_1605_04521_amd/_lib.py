@@ -33,6 +33,7 @@ MXW_KRYLOV_BLOCK = 1
 MXW_PREC_ORAS = 0
 MXW_PREC_OAS = 1
 MXW_PREC_RAS = 2
+MXW_PREC_ORAS_MULT = 3
 
 
 class MxwError(RuntimeError):
@@ -72,6 +73,11 @@ class LayoutInfo(C.Structure):
                 ("sum_ns3", C.c_double), ("n_iface", C.c_int64), ("n_imp_faces", C.c_int64)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("spmv_group", C.c_int32), ("multi_ku", C.c_int32), ("spmv_ms", C.c_double * 4),
+                ("multi_ms", C.c_double * 2)]
+
+
 _lib = None
 
 _SIGS = {
@@ -102,6 +108,15 @@ _SIGS = {
     "mxw_solve_rhs": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(SolveOpts), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
     "mxw_solve_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "mxw_problem_tune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(Tuning)]),
+    "mxw_problem_set_tiles": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "mxw_solve_recycle": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mxw_recycle_reset": (C.c_int32, [C.c_void_p]),
+    "mxw_recycle_export": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
+    "mxw_recycle_stats": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]),
     "mxw_set_timing": (C.c_int32, [C.c_int32]),
     "mxw_get_timing": (C.c_int32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "mxw_reset_timing": (C.c_int32, []),

@@ -189,6 +189,52 @@ class Problem:
         status = B.check(st, allowed)
         return x, it, rr, status
 
+    def solve_recycle(self, b, k: int = 10, tol=1e-8, restart=50, max_iters=5000, allow_notconv=False):
+        """GCRO-DR solves of the columns of b one after another, with the
+        problem's recycled space of k vectors carried between them (and to
+        later calls, also across set_medium)."""
+        import torch
+        b = b.contiguous()
+        nrhs = b.shape[0]
+        x = torch.empty_like(b)
+        it = np.zeros(nrhs, np.int32)
+        rr = np.zeros(nrhs, np.float64)
+        opts = B.solve_opts(tol, restart, max_iters)
+        st = B.lib().mxw_solve_recycle(self.h, nrhs, b.data_ptr(), C.byref(opts), k, _stream(), x.data_ptr(),
+                                       it.ctypes.data, rr.ctypes.data)
+        allowed = (B.MXW_OK, B.MXW_ENOTCONV, B.MXW_EBREAKDOWN) if allow_notconv else (B.MXW_OK,)
+        status = B.check(st, allowed)
+        return x, it, rr, status
+
+    def recycle_reset(self):
+        B.check(B.lib().mxw_recycle_reset(self.h))
+
+    def recycle_space(self):
+        """(U, Ubar, C) of the recycled space as device tensors [dim][ndof]."""
+        import torch
+        d = C.c_int32()
+        B.check(B.lib().mxw_recycle_export(self.h, C.byref(d), None, None, None, _stream()))
+        U, Ub, Cm = (torch.empty((d.value, self.ndof), dtype=torch.complex128, device="cuda") for _ in range(3))
+        B.check(B.lib().mxw_recycle_export(self.h, C.byref(d), U.data_ptr(), Ub.data_ptr(), Cm.data_ptr(),
+                                           _stream()))
+        return U, Ub, Cm
+
+    def recycle_stats(self) -> dict:
+        r, d, f = C.c_int64(), C.c_int64(), C.c_int64()
+        B.check(B.lib().mxw_recycle_stats(self.h, C.byref(r), C.byref(d), C.byref(f)))
+        return {"refreshes": r.value, "deflations": d.value, "failures": f.value}
+
+    def tune(self, nrhs: int = 1) -> dict:
+        """Time the SpMV lanes-per-row and multi-column k slice choices on this
+        problem and keep the fastest for later calls."""
+        t = B.Tuning()
+        B.check(B.lib().mxw_problem_tune(self.h, nrhs, _stream(), C.byref(t)))
+        return {"spmv_group": t.spmv_group, "multi_ku": t.multi_ku, "spmv_ms": list(t.spmv_ms),
+                "multi_ms": list(t.multi_ms)}
+
+    def set_tiles(self, spmv_group: int = 0, multi_ku: int = 0):
+        B.check(B.lib().mxw_problem_set_tiles(self.h, spmv_group, multi_ku))
+
     def history(self, col: int = 0) -> np.ndarray:
         """Relative residual estimates of every Arnoldi step of the last solve."""
         n = C.c_int32()

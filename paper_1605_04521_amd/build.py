@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmxw.so")
-SOURCES = ["basis.cpp", "layout.cpp", "fem_kernels.hip", "lu_kernels.hip", "solve_kernels.hip", "multi_solve.hip", "block_krylov.hip", "api.hip"]
+SOURCES = ["basis.cpp", "layout.cpp", "fem_kernels.hip", "lu_kernels.hip", "solve_kernels.hip", "multi_solve.hip", "block_krylov.hip", "recycle_kernels.hip", "api.hip"]
 
 
 def hipcc_cmd(out: str, extra=()):

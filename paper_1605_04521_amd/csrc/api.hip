@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -247,6 +248,30 @@ struct BlockWork {
   int64_t deflated = 0;  // block steps with a floor pivot in the Cholesky QR
 };
 
+// Krylov recycling (GCRO-DR) state, kept across solves: the basis array
+// VC = [C | V_0 .. V_steps] (C: the dim recycled vectors), U and Ubar =
+// M^{-1} U beside it, and the small cycle matrices.
+struct RecycleWork {
+  int k = 0, m = 0, dim = 0;
+  int64_t ndof = 0;
+  uint64_t gen = 0;   // operator generation C = A Ubar was made for
+  DevMem mem;
+  double2 *VC = nullptr, *Zs = nullptr, *U = nullptr, *Ub = nullptr, *Ut = nullptr, *Ubt = nullptr, *Ct = nullptr;
+  double2 *W = nullptr, *R = nullptr, *YS = nullptr;
+  double2 *h1 = nullptr, *h2 = nullptr, *part = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+  double2 *t = nullptr, *G = nullptr, *WVg = nullptr, *UU = nullptr, *Mc = nullptr, *Mu = nullptr, *mu = nullptr;
+  double *cs = nullptr, *w0 = nullptr, *hn = nullptr, *npart = nullptr, *est = nullptr, *beta = nullptr;
+  int *jd = nullptr, *info = nullptr, *kd = nullptr;
+  void* xbuf = nullptr;
+  double* host = nullptr;   // pinned
+  BlockWork bw;             // Gram products and Cholesky QR
+  std::vector<double> history;
+  int64_t refreshes = 0, deflations = 0, failures = 0;
+  ~RecycleWork() {
+    if (host) hipHostFree(host);
+  }
+};
+
 struct mxw_problem {
   explicit mxw_problem(std::shared_ptr<LayoutShared> s) : S(std::move(s)), L(S->L) {}
   std::shared_ptr<LayoutShared> S;
@@ -287,8 +312,11 @@ struct mxw_problem {
   bool factored = false;
   bool mixed = false;
   int spmv_group = 16;
+  int multi_ku = 8;       // k slice width of the multi-column local solve (tunable)
+  uint64_t op_gen = 0;    // bumped whenever A or M changes (recycled spaces go stale)
   KrylovWork kw;
   BlockWork bw;
+  RecycleWork rw;
 };
 
 namespace {
@@ -395,6 +423,10 @@ uint64_t base_bytes(const Layout& L) {
   return b;
 }
 
+// variants whose prolongation gathers every local solution of an unknown
+// (OAS: D_s = I; ORAS_MULT: weights by multiplicity) instead of the owner's
+bool gathered(int variant) { return variant == MXW_PREC_OAS || variant == MXW_PREC_ORAS_MULT; }
+
 mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   KrylovWork& k = P->kw;
   if (k.nrhs >= nrhs && k.m == m && k.ndof == P->L.ndof && k.V) return MXW_OK;
@@ -415,7 +447,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   k.W = k.mem.alloc<double2>((size_t)nrhs * n);
   k.X = k.mem.alloc<double2>((size_t)nrhs * n);
   k.Rv = k.mem.alloc<double2>((size_t)nrhs * n);
-  k.YS = P->variant == MXW_PREC_OAS ? k.mem.alloc<double2>((size_t)nrhs * P->L.sum_ns) : nullptr;
+  k.YS = gathered(P->variant) ? k.mem.alloc<double2>((size_t)nrhs * P->L.sum_ns) : nullptr;
   k.h1 = k.mem.alloc<double2>((size_t)nrhs * maxv);
   k.h2 = k.mem.alloc<double2>((size_t)nrhs * maxv);
   k.part = k.mem.alloc<double2>((size_t)nrhs * nblk * maxv);
@@ -433,13 +465,13 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   k.jd = k.mem.alloc<int>(nrhs);
   if (!k.V || !k.Z || !k.W || !k.X || !k.Rv || !k.h1 || !k.h2 || !k.part || !k.H || !k.sn || !k.g || !k.y ||
       !k.cs || !k.hn || !k.w0 || !k.npart || !k.est || !k.beta || !k.active || !k.jd ||
-      (P->variant == MXW_PREC_OAS && !k.YS)) {
+      (gathered(P->variant) && !k.YS)) {
     k.V = nullptr;
     set_error("Krylov workspace allocation failed");
     return MXW_ENOMEM;
   }
   k.xbuf = nullptr;
-  if (nrhs >= 2 && P->variant != MXW_PREC_OAS) {
+  if (nrhs >= 2 && !gathered(P->variant)) {
     const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
     k.xbuf = k.mem.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() * (P->mixed ? 4 : 8));
     if (!k.xbuf) {
@@ -458,30 +490,32 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
 // z = M^{-1} v for ncol columns (device, stride ndof)
 void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vstride, double2* z, int64_t zstride,
                     int ncol, const int* active, double2* ys, void* xbuf = nullptr) {
-  if (xbuf && ncol >= 2 && P->variant != MXW_PREC_OAS) {
+  if (xbuf && ncol >= 2 && !gathered(P->variant)) {
     ScopedKernelTimer tm("local_solve_multi");
     LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
                      P->order};
     if (P->mixed)
       launch_local_solve_multi<float>(st, a, (const float*)P->F, v, vstride, z, zstride, (float*)xbuf, P->L.sum_ns,
-                                      ncol, active);
+                                      ncol, active, P->multi_ku);
     else
       launch_local_solve_multi<double>(st, a, (const double*)P->F, v, vstride, z, zstride, (double*)xbuf,
-                                       P->L.sum_ns, ncol, active);
+                                       P->L.sum_ns, ncol, active, P->multi_ku);
     return;
   }
   ScopedKernelTimer tm("local_solve");
   LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
                    P->order};
   const int64_t n = P->L.ndof;
-  const bool oas = P->variant == MXW_PREC_OAS;
+  const bool oas = gathered(P->variant);
   if (P->mixed)
     launch_local_solve<float>(st, a, (const float*)P->F, v, vstride, z, zstride, oas ? ys : nullptr, P->L.sum_ns, ncol,
                               active);
   else
     launch_local_solve<double>(st, a, (const double*)P->F, v, vstride, z, zstride, oas ? ys : nullptr, P->L.sum_ns,
                                ncol, active);
-  if (oas) launch_gather_all(st, n, P->gall_ptr, P->gall_pos, ys, P->L.sum_ns, z, zstride, ncol, active);
+  if (oas)
+    launch_gather_all(st, n, P->gall_ptr, P->gall_pos, ys, P->L.sum_ns, z, zstride, ncol, active,
+                      P->variant == MXW_PREC_ORAS_MULT);
 }
 
 void spmv_dev(mxw_problem* P, hipStream_t st, const double2* x, double2* y, const double2* b, int ncol,
@@ -541,6 +575,7 @@ mxw_status factor_impl(mxw_problem* P, hipStream_t st) {
   HIP_CHECK(hipMemcpyAsync(info.data(), P->info, sizeof(int) * info.size(), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   P->factored = true;
+  ++P->op_gen;
   for (int s = 0; s < P->L.n_sub; ++s)
     if (info[s] != 0) {
       std::ostringstream os;
@@ -789,6 +824,7 @@ mxw_status assemble_medium(mxw_problem* P, const double* eps, double k0, hipStre
     HIP_CHECK(hipMemcpyAsync(P->sub_face_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, st));
   P->k0 = k0;
   P->factored = false;
+  ++P->op_gen;
   {
     ScopedTimer tm(st, "assemble");
     launch_element(st, L.nt, P->xyz, P->tets, P->eps, P->phi, P->curl, nloc, L.basis.ncurl_max, k0 * k0, P->AT);
@@ -813,7 +849,8 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
     set_error("unknown precision");
     return MXW_EINVAL;
   }
-  if (variant != MXW_PREC_ORAS && variant != MXW_PREC_OAS && variant != MXW_PREC_RAS) {
+  if (variant != MXW_PREC_ORAS && variant != MXW_PREC_OAS && variant != MXW_PREC_RAS &&
+      variant != MXW_PREC_ORAS_MULT) {
     set_error("unknown preconditioner variant");
     return MXW_EINVAL;
   }
@@ -928,9 +965,7 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
 // ---------------------------------------------------------------------------
 constexpr int kMaxGramParts = 128;   // split-K partial products of a Gram matrix
 
-mxw_status ensure_block(mxw_problem* P, int p, int m) {
-  BlockWork& b = P->bw;
-  const int64_t n = P->L.ndof;
+mxw_status ensure_block_ws(BlockWork& b, int64_t n, int p, int m) {
   if (b.p == p && b.m == m && b.ndof == n && b.H1) return MXW_OK;
   b.mem.reset();
   b.p = p;
@@ -964,11 +999,12 @@ mxw_status ensure_block(mxw_problem* P, int p, int m) {
   return MXW_OK;
 }
 
+mxw_status ensure_block(mxw_problem* P, int p, int m) { return ensure_block_ws(P->bw, P->L.ndof, p, m); }
+
 // out (Q x p, column-major) = A^H W, A: Q vectors of length n, W: p vectors,
 // as split-K partial products summed in a fixed order
-mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const double2* W, int p, double2* out) {
-  BlockWork& b = P->bw;
-  const int64_t n = P->L.ndof;
+mxw_status gram(BlockWork& b, int64_t n, hipStream_t st, const double2* A, int Q, const double2* W, int p,
+                double2* out) {
   // about 2048 workgroups, within the partial-product buffer (sized for
   // kMaxGramParts parts of the largest Q)
   const int qtiles = (Q + 63) / 64;
@@ -977,6 +1013,10 @@ mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const d
   launch_bgram(st, A, Q, W, p, n, want, b.part);
   launch_gram_reduce(st, (int64_t)Q * p, bgram_parts(n, want), b.part, out);
   return MXW_OK;
+}
+
+mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const double2* W, int p, double2* out) {
+  return gram(P->bw, P->L.ndof, st, A, Q, W, p, out);
 }
 
 // C (n x p) = alpha A M + beta C; A: K vectors of length n, M: K x p (ld ldm)
@@ -988,13 +1028,13 @@ mxw_status tall_gemm(mxw_problem* P, hipStream_t st, const double2* A, int K, co
 
 // out = in S^{-1} with orthonormal columns (Cholesky QR twice); tmp: n x p.
 // have_gram: b.G already holds in^H in.
-mxw_status cholqr2(mxw_problem* P, hipStream_t st, const double2* in, double2* tmp, double2* out, int p,
+mxw_status cholqr2(mxw_problem* P, BlockWork& b, hipStream_t st, const double2* in, double2* tmp, double2* out, int p,
                    bool have_gram = false) {
-  BlockWork& b = P->bw;
-  if (!have_gram) TRY(gram(P, st, in, p, in, p, b.G));
+  const int64_t n = P->L.ndof;
+  if (!have_gram) TRY(gram(b, n, st, in, p, in, p, b.G));
   launch_chol(st, p, b.G, b.R1, b.R1i, nullptr, nullptr, b.info);
   TRY(tall_gemm(P, st, in, p, b.R1i, p, p, 1.0, 0.0, tmp));
-  TRY(gram(P, st, tmp, p, tmp, p, b.G));
+  TRY(gram(b, n, st, tmp, p, tmp, p, b.G));
   launch_chol(st, p, b.G, b.R2, b.R2i, b.R1, b.S, b.info);
   TRY(tall_gemm(P, st, tmp, p, b.R2i, p, p, 1.0, 0.0, out));
   return MXW_OK;
@@ -1031,7 +1071,7 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
   while (!conv && steps < opts->max_iters && !breakdown) {
     // V_0 S0 = R
     HIP_CHECK(hipMemsetAsync(b.info, 0, sizeof(int), st));
-    TRY(cholqr2(P, st, k.Rv, k.W, k.V, p));
+    TRY(cholqr2(P, P->bw, st, k.Rv, k.W, k.V, p));
     launch_set_e(st, p, ldE, b.S, b.E);
     int jd = 0;
     for (int j = 0; j < m; ++j) {
@@ -1060,7 +1100,7 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
         TRY(tall_gemm(P, st, k.V, Q, b.H2, Q, p, -1.0, 1.0, k.W));
       }
       // V_{j+1} S = W
-      TRY(cholqr2(P, st, k.W, k.Rv, k.V + (int64_t)(j + 1) * p * n, p, !again));
+      TRY(cholqr2(P, P->bw, st, k.W, k.Rv, k.V + (int64_t)(j + 1) * p * n, p, !again));
       launch_bls_step(st, j, p, m, b.H1, again ? b.H2 : nullptr, b.S, b.Hc, b.T, b.Rls, b.E, b.est);
       HIP_CHECK(hipGetLastError());
       HIP_CHECK(hipMemcpyAsync(hbuf, b.est, sizeof(double) * p, hipMemcpyDeviceToHost, st));
@@ -1131,6 +1171,260 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
     return MXW_EBREAKDOWN;
   }
   set_error("max_iters reached before the tolerance");
+  return MXW_ENOTCONV;
+}
+
+
+// ---------------------------------------------------------------------------
+// Krylov subspace recycling: GCRO-DR over the systems solved on a problem
+// (Sec. 6 proposes it for the slowly varying systems of the imaging loop)
+// ---------------------------------------------------------------------------
+mxw_status ensure_recycle(mxw_problem* P, int k, int m) {
+  RecycleWork& w = P->rw;
+  const int64_t n = P->L.ndof;
+  if (w.VC && w.k == k && w.m == m && w.ndof == n) return MXW_OK;
+  w.mem.reset();
+  w.VC = nullptr;
+  w.dim = 0;
+  w.k = k;
+  w.m = m;
+  w.ndof = n;
+  const int maxv = m + 1, nblk = red_blocks(n);
+  const bool gath = gathered(P->variant);
+  w.VC = w.mem.alloc<double2>((size_t)maxv * n);
+  w.Zs = w.mem.alloc<double2>((size_t)m * n);
+  w.U = w.mem.alloc<double2>((size_t)k * n);
+  w.Ub = w.mem.alloc<double2>((size_t)k * n);
+  w.Ut = w.mem.alloc<double2>((size_t)k * n);
+  w.Ubt = w.mem.alloc<double2>((size_t)k * n);
+  w.Ct = w.mem.alloc<double2>((size_t)k * n);
+  w.W = w.mem.alloc<double2>(n);
+  w.R = w.mem.alloc<double2>(n);
+  w.YS = gath ? w.mem.alloc<double2>((size_t)k * P->L.sum_ns) : nullptr;
+  w.h1 = w.mem.alloc<double2>(maxv);
+  w.h2 = w.mem.alloc<double2>(maxv);
+  w.part = w.mem.alloc<double2>((size_t)nblk * maxv);
+  w.H = w.mem.alloc<double2>((size_t)maxv * m);
+  w.sn = w.mem.alloc<double2>(maxv);
+  w.g = w.mem.alloc<double2>(maxv + 1);
+  w.y = w.mem.alloc<double2>(maxv);
+  w.t = w.mem.alloc<double2>(kRecycleLd);
+  w.G = w.mem.alloc<double2>((size_t)kRecycleLd * kRecycleMaxCycle);
+  w.WVg = w.mem.alloc<double2>((size_t)kRecycleLd * k);
+  w.UU = w.mem.alloc<double2>((size_t)k * k);
+  w.Mc = w.mem.alloc<double2>((size_t)kRecycleLd * k);
+  w.Mu = w.mem.alloc<double2>((size_t)kRecycleLd * k);
+  w.mu = w.mem.alloc<double2>(kRecycleLd);
+  w.cs = w.mem.alloc<double>(maxv);
+  w.w0 = w.mem.alloc<double>(1);
+  w.hn = w.mem.alloc<double>(1);
+  w.npart = w.mem.alloc<double>(nblk);
+  w.est = w.mem.alloc<double>(1);
+  w.beta = w.mem.alloc<double>(1);
+  w.jd = w.mem.alloc<int>(1);
+  w.kd = w.mem.alloc<int>(1);
+  w.info = w.mem.alloc<int>(1);
+  w.xbuf = nullptr;
+  bool ok = w.VC && w.Zs && w.U && w.Ub && w.Ut && w.Ubt && w.Ct && w.W && w.R && (!gath || w.YS) && w.h1 && w.h2 &&
+            w.part && w.H && w.sn && w.g && w.y && w.t && w.G && w.WVg && w.UU && w.Mc && w.Mu && w.mu && w.cs &&
+            w.w0 && w.hn && w.npart && w.est && w.beta && w.jd && w.kd && w.info;
+  if (ok && k >= 2 && !gath) {
+    const int nchunk = (k + multi_chunk_cols() - 1) / multi_chunk_cols();
+    w.xbuf = w.mem.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() * (P->mixed ? 4 : 8));
+    ok = w.xbuf != nullptr;
+  }
+  if (ok && !w.host) ok = hipHostMalloc((void**)&w.host, sizeof(double) * 8) == hipSuccess;
+  if (ok) ok = ensure_block_ws(w.bw, n, k, (m + k) / k + 1) == MXW_OK;
+  if (!ok) {
+    w.mem.reset();
+    w.VC = nullptr;
+    set_error("recycling workspace allocation failed");
+    return MXW_ENOMEM;
+  }
+  return MXW_OK;
+}
+
+// host copy of a few device doubles (one synchronisation)
+mxw_status fetch(hipStream_t st, double* host, std::initializer_list<const double*> src) {
+  int i = 0;
+  for (const double* p : src) HIP_CHECK(hipMemcpyAsync(host + i++, p, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return MXW_OK;
+}
+
+mxw_status set_int(hipStream_t st, int* dev, int v) {
+  HIP_CHECK(hipMemcpyAsync(dev, &v, sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipStreamSynchronize(st));   // v lives on the host stack
+  return MXW_OK;
+}
+
+// Carry the recycled space to a new operator: Ubar = M^{-1} U, C = A Ubar,
+// C = Q R (Cholesky QR twice), C <- Q, U <- U R^{-1}, Ubar <- Ubar R^{-1}.
+mxw_status recycle_refresh(mxw_problem* P, hipStream_t st) {
+  RecycleWork& w = P->rw;
+  const int64_t n = P->L.ndof;
+  const int d = w.dim;
+  apply_prec_dev(P, st, w.U, n, w.Ub, n, d, nullptr, w.YS, d >= 2 ? w.xbuf : nullptr);
+  {
+    ScopedKernelTimer tm("spmv");
+    launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, w.Ub, n, w.VC, n, nullptr, 0, d, nullptr);
+  }
+  TRY(cholqr2(P, w.bw, st, w.VC, w.Ct, w.VC, d));
+  TRY(tall_gemm(P, st, w.U, d, w.bw.R1i, d, d, 1.0, 0.0, w.Ut));
+  TRY(tall_gemm(P, st, w.Ut, d, w.bw.R2i, d, d, 1.0, 0.0, w.U));
+  TRY(tall_gemm(P, st, w.Ub, d, w.bw.R1i, d, d, 1.0, 0.0, w.Ubt));
+  TRY(tall_gemm(P, st, w.Ubt, d, w.bw.R2i, d, d, 1.0, 0.0, w.Ub));
+  HIP_CHECK(hipGetLastError());
+  w.gen = P->op_gen;
+  ++w.refreshes;
+  return MXW_OK;
+}
+
+// Deflated restart after a cycle with kk recycled vectors and jd Arnoldi
+// steps: the new space from the harmonic Ritz vectors of the cycle.
+mxw_status recycle_deflate(mxw_problem* P, hipStream_t st, int kk, int jd, bool last_row) {
+  RecycleWork& w = P->rw;
+  const int64_t n = P->L.ndof;
+  const int s = kk + jd, knew = std::min(w.k, s);
+  if (knew == 0) return MXW_OK;
+  if (kk) {
+    TRY(gram(w.bw, n, st, w.VC, s + 1, w.U, kk, w.WVg));
+    TRY(gram(w.bw, n, st, w.U, kk, w.U, kk, w.UU));
+  }
+  launch_rc_ritz(st, kk, jd, knew, last_row ? 1 : 0, w.G, w.WVg, w.UU, w.Mc, w.Mu, w.mu, w.info);
+  HIP_CHECK(hipGetLastError());
+  int info = 0;
+  HIP_CHECK(hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (info) {   // no usable Schur form: continue without a recycled space
+    w.dim = 0;
+    ++w.failures;
+    return MXW_OK;
+  }
+  const int rows = s + (last_row ? 1 : 0);
+  const int ld = kRecycleLd;
+  TRY(tall_gemm(P, st, w.VC, rows, w.Mc, ld, knew, 1.0, 0.0, w.Ct));
+  TRY(tall_gemm(P, st, w.U, kk, w.Mu, ld, knew, 1.0, 0.0, w.Ut));
+  TRY(tall_gemm(P, st, w.VC + (int64_t)kk * n, jd, w.Mu + kk, ld, knew, 1.0, kk ? 1.0 : 0.0, w.Ut));
+  TRY(tall_gemm(P, st, w.Ub, kk, w.Mu, ld, knew, 1.0, 0.0, w.Ubt));
+  TRY(tall_gemm(P, st, w.Zs, jd, w.Mu + kk, ld, knew, 1.0, kk ? 1.0 : 0.0, w.Ubt));
+  HIP_CHECK(hipMemcpyAsync(w.VC, w.Ct, sizeof(double2) * knew * n, hipMemcpyDeviceToDevice, st));
+  HIP_CHECK(hipGetLastError());
+  std::swap(w.U, w.Ut);
+  std::swap(w.Ub, w.Ubt);
+  w.dim = knew;
+  w.gen = P->op_gen;
+  ++w.deflations;
+  return MXW_OK;
+}
+
+// One system A x = b by GCRO-DR with the problem's recycled space.
+mxw_status recycle_solve_one(mxw_problem* P, hipStream_t st, const double2* b, double2* x, const mxw_solve_opts* opts,
+                             int* iters_out, double* relres_out, bool* brk_any) {
+  RecycleWork& w = P->rw;
+  const int64_t n = P->L.ndof;
+  const int m = w.m, maxv = m + 1;
+  double* hb = w.host;
+  HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double2) * n, st));
+  launch_norm(st, n, b, n, w.npart, w.beta, 1, nullptr);
+  TRY(fetch(st, hb, {w.beta}));
+  const double bnorm = hb[0];
+  w.history.clear();
+  *iters_out = 0;
+  *relres_out = 0.0;
+  if (!(bnorm > 0)) return MXW_OK;
+  if (w.dim && w.gen != P->op_gen) TRY(recycle_refresh(P, st));
+  HIP_CHECK(hipMemcpyAsync(w.R, b, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+  int iters = 0;
+  double relres = 1.0;
+  bool conv = false;
+  while (true) {
+    const int kk = w.dim;
+    if (kk) {   // minimal residual correction over range(U): t = C^H r
+      TRY(set_int(st, w.kd, kk));
+      launch_dots(st, n, kk, w.VC, 0, w.R, n, w.part, maxv, 1, nullptr);
+      launch_reduce_dots(st, n, kk, w.part, w.t, maxv, 0, 1, nullptr);
+      launch_xupdate(st, n, w.kd, w.Ub, 0, w.t, maxv, x, n, 1);
+      launch_update(st, n, kk, w.VC, 0, w.R, n, w.t, maxv, 1, nullptr);
+    }
+    launch_norm(st, n, w.R, n, w.npart, w.beta, 1, nullptr);
+    TRY(fetch(st, hb, {w.beta}));
+    const double beta = hb[0];
+    if (beta <= opts->tol * bnorm) {
+      spmv_dev(P, st, x, w.W, b, 1, nullptr);
+      launch_norm(st, n, w.W, n, w.npart, w.w0, 1, nullptr);
+      TRY(fetch(st, hb, {w.w0}));
+      relres = hb[0] / bnorm;
+      if (relres <= opts->tol || beta == 0.0) {
+        conv = relres <= opts->tol;
+        break;
+      }
+    }
+    const int steps = m - kk;
+    launch_scale_inv(st, n, w.R, n, w.VC + (int64_t)kk * n, 0, w.beta, 1, nullptr);
+    {
+      std::vector<double2> g0(maxv + 1, make_double2(0.0, 0.0));
+      g0[0] = make_double2(beta, 0.0);
+      HIP_CHECK(hipMemcpyAsync(w.g, g0.data(), sizeof(double2) * g0.size(), hipMemcpyHostToDevice, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+    int jdone = 0;
+    bool brk = false;
+    for (int j = 0; j < steps; ++j) {
+      double2* Vj = w.VC + (int64_t)(kk + j) * n;
+      double2* Zj = w.Zs + (int64_t)j * n;
+      const int nvec = kk + j + 1;
+      apply_prec_dev(P, st, Vj, n, Zj, n, 1, nullptr, w.YS, nullptr);
+      {
+        ScopedKernelTimer tm("spmv");
+        launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, n, w.W, n, nullptr, 0, 1, nullptr);
+      }
+      launch_norm(st, n, w.W, n, w.npart, w.w0, 1, nullptr);
+      // against [C, V_0..V_j] twice (CGS2); h1 = [B_j; h_j]
+      launch_dots(st, n, nvec, w.VC, 0, w.W, n, w.part, maxv, 1, nullptr);
+      launch_reduce_dots(st, n, nvec, w.part, w.h1, maxv, 0, 1, nullptr);
+      launch_update(st, n, nvec, w.VC, 0, w.W, n, w.h1, maxv, 1, nullptr);
+      launch_dots(st, n, nvec, w.VC, 0, w.W, n, w.part, maxv, 1, nullptr);
+      launch_reduce_dots(st, n, nvec, w.part, w.h2, maxv, 0, 1, nullptr);
+      launch_update(st, n, nvec, w.VC, 0, w.W, n, w.h2, maxv, 1, nullptr);
+      launch_reduce_dots(st, n, nvec, w.part, w.h1, maxv, 1, 1, nullptr);
+      launch_norm(st, n, w.W, n, w.npart, w.hn, 1, nullptr);
+      launch_rc_save(st, kk, j, w.h1, w.hn, w.G);
+      launch_givens(st, 1, j, maxv, w.h1 + kk, w.hn, w.H, m, w.cs, w.sn, w.g, w.est, nullptr);
+      launch_scale_inv(st, n, w.W, n, w.VC + (int64_t)(nvec)*n, 0, w.hn, 1, nullptr);
+      HIP_CHECK(hipGetLastError());
+      TRY(fetch(st, hb, {w.est, w.hn, w.w0}));
+      const double est = hb[0], hn = hb[1], w0 = hb[2];
+      ++iters;
+      jdone = j + 1;
+      w.history.push_back(est / bnorm);
+      brk = !(hn > 1e-14 * w0);
+      if (brk) *brk_any = true;
+      if (est <= opts->tol * bnorm || brk || iters >= opts->max_iters || !std::isfinite(est)) break;
+    }
+    // x += Z y - Ubar (B y)
+    TRY(set_int(st, w.jd, jdone));
+    launch_backsolve(st, 1, w.jd, maxv, w.H, m, w.g, w.y);
+    launch_xupdate(st, n, w.jd, w.Zs, 0, w.y, maxv, x, n, 1);
+    if (kk) {
+      launch_rc_by(st, kk, w.jd, w.G, w.y, w.t);
+      launch_xupdate(st, n, w.kd, w.Ub, 0, w.t, maxv, x, n, 1);
+    }
+    TRY(recycle_deflate(P, st, kk, jdone, !brk));
+    spmv_dev(P, st, x, w.R, b, 1, nullptr);
+    launch_norm(st, n, w.R, n, w.npart, w.beta, 1, nullptr);
+    HIP_CHECK(hipGetLastError());
+    TRY(fetch(st, hb, {w.beta}));
+    relres = hb[0] / bnorm;
+    if (relres <= opts->tol) {
+      conv = true;
+      break;
+    }
+    if (iters >= opts->max_iters || !std::isfinite(relres)) break;
+  }
+  *iters_out = iters;
+  *relres_out = relres;
+  if (conv) return MXW_OK;
   return MXW_ENOTCONV;
 }
 
@@ -1347,8 +1641,9 @@ mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double*
   hipStream_t st = (hipStream_t)stream;
   double2* ys = nullptr;
   void* xbuf = nullptr;
-  if (prob->variant == MXW_PREC_OAS) HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
-  if (prob->variant != MXW_PREC_OAS && nrhs >= 2) {
+  if (gathered(prob->variant))
+    HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
+  if (!gathered(prob->variant) && nrhs >= 2) {
     const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
     HIP_CHECK(hipMallocAsync(&xbuf, (size_t)nchunk * 2 * prob->L.sum_ns * multi_chunk_cols() * (prob->mixed ? 4 : 8), st));
   }
@@ -1573,6 +1868,153 @@ mxw_status mxw_solve(mxw_problem* P, int32_t nrhs, const mxw_source* src, const 
   hipFree(b);
   if (!E_out_is_device) hipFree(x);
   return s;
+}
+
+mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t multi_ku) {
+  TRY(check_problem(P));
+  const bool g_ok = spmv_group == 0 || spmv_group == 4 || spmv_group == 8 || spmv_group == 16 || spmv_group == 32;
+  const bool k_ok = multi_ku == 0 || multi_ku == 4 || multi_ku == 8;
+  if (!g_ok || !k_ok) {
+    set_error("spmv_group must be 0, 4, 8, 16 or 32 and multi_ku 0, 4 or 8");
+    return MXW_EINVAL;
+  }
+  if (spmv_group) P->spmv_group = spmv_group;
+  if (multi_ku) P->multi_ku = multi_ku;
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuning* out) {
+  TRY(check_problem(P));
+  if (nrhs < 1 || nrhs > 4096) {
+    set_error("nrhs must be in 1..4096");
+    return MXW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = P->L.ndof;
+  DevMem tmp;
+  double2* x = tmp.alloc<double2>((size_t)n * nrhs);
+  double2* y = tmp.alloc<double2>((size_t)n * nrhs);
+  if (!x || !y) {
+    set_error("device allocation failed (tuning buffers)");
+    return MXW_ENOMEM;
+  }
+  HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double2) * n * nrhs, st));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIP_CHECK(hipEventCreate(&ea));
+  HIP_CHECK(hipEventCreate(&eb));
+  // average of 3 launches after one untimed launch
+  auto time_ms = [&](const std::function<void()>& fn) -> double {
+    fn();
+    hipEventRecord(ea, st);
+    for (int r = 0; r < 3; ++r) fn();
+    hipEventRecord(eb, st);
+    hipEventSynchronize(eb);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ea, eb);
+    return ms / 3.0;
+  };
+  mxw_tuning t{};
+  const int groups[4] = {4, 8, 16, 32};
+  int best = 0;
+  for (int g = 0; g < 4; ++g) {
+    t.spmv_ms[g] = time_ms([&] {
+      launch_spmv(st, groups[g], n, P->rowptr, P->cols, P->vals, x, n, y, n, nullptr, 0, nrhs, nullptr);
+    });
+    if (t.spmv_ms[g] < t.spmv_ms[best]) best = g;
+  }
+  P->spmv_group = groups[best];
+  t.spmv_group = P->spmv_group;
+  if (nrhs >= 2 && !gathered(P->variant) && P->factored) {
+    const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
+    void* xbuf = tmp.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() *
+                                          (P->mixed ? 4 : 8));
+    if (!xbuf) {
+      hipEventDestroy(ea);
+      hipEventDestroy(eb);
+      set_error("device allocation failed (tuning scratch)");
+      return MXW_ENOMEM;
+    }
+    const int kus[2] = {4, 8};
+    int bk = 1;
+    for (int q = 0; q < 2; ++q) {
+      P->multi_ku = kus[q];
+      t.multi_ms[q] = time_ms([&] { apply_prec_dev(P, st, x, n, y, n, nrhs, nullptr, nullptr, xbuf); });
+      if (t.multi_ms[q] < t.multi_ms[bk]) bk = q;
+    }
+    P->multi_ku = kus[bk];
+  }
+  t.multi_ku = P->multi_ku;
+  hipEventDestroy(ea);
+  hipEventDestroy(eb);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (out) *out = t;
+  return MXW_OK;
+}
+
+mxw_status mxw_solve_recycle(mxw_problem* P, int32_t nrhs, const double* b_dev, const mxw_solve_opts* opts, int32_t k,
+                             void* stream, double* x_dev, int32_t* iters_out, double* relres_out) {
+  TRY(check_problem(P));
+  if (nrhs < 1 || !b_dev || !x_dev || !opts) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  if (k < 1 || k > kRecycleMaxK || opts->restart <= k || opts->restart > kRecycleMaxCycle || opts->max_iters < 1 ||
+      !(opts->tol > 0)) {
+    set_error("invalid recycling options (1 <= k <= 32, k < restart <= 64, max_iters >= 1, tol > 0)");
+    return MXW_EINVAL;
+  }
+  if (!P->factored) {
+    set_error("problem is not factorised");
+    return MXW_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  TRY(ensure_recycle(P, k, opts->restart));
+  const int64_t n = P->L.ndof;
+  mxw_status result = MXW_OK;
+  bool brk = false;
+  for (int c = 0; c < nrhs; ++c) {
+    int it = 0;
+    double rr = 0.0;
+    const mxw_status r = recycle_solve_one(P, st, (const double2*)b_dev + (int64_t)c * n,
+                                           (double2*)x_dev + (int64_t)c * n, opts, &it, &rr, &brk);
+    if (iters_out) iters_out[c] = it;
+    if (relres_out) relres_out[c] = rr;
+    if (r == MXW_ENOTCONV) result = brk ? MXW_EBREAKDOWN : MXW_ENOTCONV;
+    else if (r != MXW_OK) return r;
+  }
+  if (result == MXW_ENOTCONV) set_error("max_iters reached before the tolerance");
+  if (result == MXW_EBREAKDOWN) set_error("Krylov breakdown before the tolerance");
+  return result;
+}
+
+mxw_status mxw_recycle_reset(mxw_problem* P) {
+  TRY(check_problem(P));
+  P->rw.dim = 0;
+  return MXW_OK;
+}
+
+mxw_status mxw_recycle_export(mxw_problem* P, int32_t* dim, double* U_dev, double* Ubar_dev, double* C_dev,
+                              void* stream) {
+  TRY(check_problem(P));
+  const RecycleWork& w = P->rw;
+  const int d = w.VC ? w.dim : 0;
+  if (dim) *dim = d;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = sizeof(double2) * (size_t)d * P->L.ndof;
+  if (d && U_dev) HIP_CHECK(hipMemcpyAsync(U_dev, w.U, bytes, hipMemcpyDeviceToDevice, st));
+  if (d && Ubar_dev) HIP_CHECK(hipMemcpyAsync(Ubar_dev, w.Ub, bytes, hipMemcpyDeviceToDevice, st));
+  if (d && C_dev) HIP_CHECK(hipMemcpyAsync(C_dev, w.VC, bytes, hipMemcpyDeviceToDevice, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return MXW_OK;
+}
+
+mxw_status mxw_recycle_stats(const mxw_problem* P, int64_t* refreshes, int64_t* deflations, int64_t* failures) {
+  TRY(check_problem(P));
+  if (refreshes) *refreshes = P->rw.refreshes;
+  if (deflations) *deflations = P->rw.deflations;
+  if (failures) *failures = P->rw.failures;
+  return MXW_OK;
 }
 
 mxw_status mxw_solve_history(const mxw_problem* P, int32_t col, double* out, int32_t max_len, int32_t* len) {

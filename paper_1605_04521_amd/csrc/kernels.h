@@ -125,10 +125,12 @@ hipError_t prepare_local_solve(size_t dyn_bytes_double, size_t dyn_bytes_float);
 // all columns at once: factor strips read once per chunk of multi_chunk_cols() columns
 template <typename R>
 void launch_local_solve_multi(hipStream_t st, const LocalSolveArgs& a, const R* F, const double2* v, int64_t vstride,
-                              double2* z, int64_t zstride, R* xbuf, int64_t sum_ns, int ncol, const int* active);
+                              double2* z, int64_t zstride, R* xbuf, int64_t sum_ns, int ncol, const int* active,
+                              int ku);
 int multi_chunk_cols();
 void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const int64_t* pos, const double2* ys,
-                       int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active);
+                       int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active,
+                       int by_multiplicity);
 
 // block GMRES: split-K Gram reduction, Cholesky + inverse of a p x p Gram
 // matrix, block Hessenberg least-squares step and back substitution
@@ -168,5 +170,15 @@ void launch_backsolve(hipStream_t st, int ncol, const int* jd, int maxv, const d
                       double2* y);
 void launch_xupdate(hipStream_t st, int64_t ndof, const int* jd, const double2* Z, int64_t zcol, const double2* y,
                     int maxv, double2* x, int64_t xcol, int ncol);
+
+// Krylov subspace recycling (GCRO-DR): Gbar columns, the recycled part of
+// the least-squares solution, and the deflated restart of a cycle
+constexpr int kRecycleMaxCycle = 64;   // largest recycled + Arnoldi vectors per cycle
+constexpr int kRecycleLd = kRecycleMaxCycle + 1;
+constexpr int kRecycleMaxK = 32;       // largest recycled dimension
+void launch_rc_save(hipStream_t st, int kk, int j, const double2* h, const double* hn, double2* G);
+void launch_rc_by(hipStream_t st, int kk, const int* jd, const double2* G, const double2* y, double2* t);
+void launch_rc_ritz(hipStream_t st, int kk, int jd, int knew, int last_row, const double2* G, const double2* WVg,
+                    const double2* UU, double2* Mc, double2* Mu, double2* mu, int* info);
 
 }  // namespace mxw

@@ -48,7 +48,7 @@ mxw_status build_layout(const mxw_problem_desc* d, Layout& L) {
   if (d->overlap_layers < 0) return fail("overlap_layers must be >= 0");
   if (!(std::isfinite(d->k0)) || d->k0 < 0) return fail("k0 must be finite and >= 0");
   if (d->precision != MXW_FP64 && d->precision != MXW_MIXED) return fail("unknown precision");
-  if (d->prec_variant < 0 || d->prec_variant > 2) return fail("unknown preconditioner variant");
+  if (d->prec_variant < 0 || d->prec_variant > MXW_PREC_ORAS_MULT) return fail("unknown preconditioner variant");
   if (d->n_vertices >= (int64_t)1 << 31 || d->n_tets >= (int64_t)1 << 31)
     return fail("mesh too large for 32-bit ids");
   if (d->n_bfaces > 0 && (!d->bfaces || !d->bface_kind)) return fail("boundary face arrays missing");

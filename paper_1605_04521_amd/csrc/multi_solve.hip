@@ -19,7 +19,7 @@ namespace mxw {
 
 constexpr int kMultiPC = 32;   // columns per chunk
 
-template <typename R, int NB, int PC>
+template <typename R, int NB, int PC, int KU>
 __global__ void __launch_bounds__(256) k_local_solve_multi(
     const R* __restrict__ F, const int64_t* __restrict__ foff, const int* __restrict__ nsz,
     const int* __restrict__ lds, const int* __restrict__ perm, const int64_t* __restrict__ poff,
@@ -28,7 +28,6 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
     const int* __restrict__ active, const int* __restrict__ order) {
   static_assert(NB == 32 && PC == 32, "tile shape assumes 32 x 32 blocks");
   constexpr int SB = 2 * NB;   // rows per pass over the factor
-  constexpr int KU = 8;        // 4-wide k steps per K slice
   typedef typename Mfma<R>::acc_t acc_t;
   __shared__ R Tr[SB][PC + 1], Ti[SB][PC + 1];       // T of the super-block
   __shared__ R Br[3][NB][NB + 1], Bi[3][NB][NB + 1];  // diagonal block solved first, coupling block, second diagonal block
@@ -226,17 +225,25 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
 
 template <typename R>
 void launch_local_solve_multi(hipStream_t st, const LocalSolveArgs& a, const R* F, const double2* v, int64_t vstride,
-                              double2* z, int64_t zstride, R* xbuf, int64_t sum_ns, int ncol, const int* active) {
+                              double2* z, int64_t zstride, R* xbuf, int64_t sum_ns, int ncol, const int* active,
+                              int ku) {
   if (a.n_sub == 0 || ncol == 0) return;
   const int nchunk = (ncol + kMultiPC - 1) / kMultiPC;
   const int64_t xchunk = 2 * sum_ns * kMultiPC;
-  timed_launch(k_local_solve_multi<R, kLuNB, kMultiPC>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F, a.foff, a.nsz,
-               a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol, active, a.order);
+  // ku: 4-wide k steps per K slice of the long product (a tuning choice)
+  if (ku == 4)
+    timed_launch(k_local_solve_multi<R, kLuNB, kMultiPC, 4>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F, a.foff,
+                 a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol, active,
+                 a.order);
+  else
+    timed_launch(k_local_solve_multi<R, kLuNB, kMultiPC, 8>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F, a.foff,
+                 a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol, active,
+                 a.order);
 }
 template void launch_local_solve_multi<double>(hipStream_t, const LocalSolveArgs&, const double*, const double2*,
-                                               int64_t, double2*, int64_t, double*, int64_t, int, const int*);
+                                               int64_t, double2*, int64_t, double*, int64_t, int, const int*, int);
 template void launch_local_solve_multi<float>(hipStream_t, const LocalSolveArgs&, const float*, const double2*,
-                                              int64_t, double2*, int64_t, float*, int64_t, int, const int*);
+                                              int64_t, double2*, int64_t, float*, int64_t, int, const int*, int);
 
 int multi_chunk_cols() { return kMultiPC; }
 

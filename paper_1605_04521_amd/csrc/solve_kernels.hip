@@ -197,13 +197,18 @@ __global__ void __launch_bounds__(256) k_local_solve(const R* __restrict__ F, co
 // z[i] = sum over the subdomains containing i of y_s (fixed order)
 __global__ void k_gather_all(int64_t ndof, const int64_t* __restrict__ ptr, const int64_t* __restrict__ pos,
                              const double2* __restrict__ ys, int64_t ystride, double2* __restrict__ z,
-                             int64_t zstride, const int* __restrict__ active) {
+                             int64_t zstride, const int* __restrict__ active, int by_multiplicity) {
   const int col = blockIdx.y;
   if (active && !active[col]) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ndof) return;
   double2 acc = make_double2(0.0, 0.0);
   for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) acc = cadd(acc, ys[(int64_t)col * ystride + pos[q]]);
+  if (by_multiplicity) {
+    // D_s = 1 / (number of subdomains containing unknown i) in every subdomain
+    const double w = 1.0 / (double)(ptr[i + 1] - ptr[i]);
+    acc = make_double2(acc.x * w, acc.y * w);
+  }
   z[(int64_t)col * zstride + i] = acc;
 }
 
@@ -551,10 +556,11 @@ hipError_t prepare_local_solve(size_t dyn_bytes_double, size_t dyn_bytes_float) 
 }
 
 void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const int64_t* pos, const double2* ys,
-                       int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active) {
+                       int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active,
+                       int by_multiplicity) {
   if (ndof == 0 || ncol == 0) return;
   hipLaunchKernelGGL(k_gather_all, dim3((unsigned)((ndof + 255) / 256), ncol), dim3(256), 0, st, ndof, ptr, pos, ys,
-                     ystride, z, zstride, active);
+                     ystride, z, zstride, active, by_multiplicity);
 }
 
 constexpr int kSpmmCols = 8;   // columns per k_spmm group

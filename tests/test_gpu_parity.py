@@ -354,3 +354,63 @@ def test_ras_variant(name):
     if name == "cube8_r1":
         _, it_oras, _, _ = Problem.from_problem(prob).solve(prob.sources[:1])
         assert it_oras[0] < it[0]
+
+
+@pytest.mark.parametrize("name", ["cube8_r1", "chamber6_r2"])
+def test_multiplicity_partition_of_unity(name):
+    """ORAS with D_s = 1 / multiplicity (the local solutions of an unknown
+    averaged over every subdomain that contains it) against the oracle: one
+    application to three columns, and the solve (iterations +-1, E 1e-6)."""
+    prob, orc = oracle_for(name)
+    say(f"[gpu] ORAS, multiplicity partition of unity, {name}")
+    orc_m = OracleSolver.from_problem(prob, "oras_mult")
+    P = Problem.from_problem(prob, variant=B.MXW_PREC_ORAS_MULT)
+    rng = np.random.default_rng(22)
+    V = rng.standard_normal((3, orc.ndof)) + 1j * rng.standard_normal((3, orc.ndof))
+    Z = to_np(P.apply_prec(torch.from_numpy(V).cuda()))
+    for c in range(3):
+        zo = orc_m.prec.apply(V[c])
+        assert np.linalg.norm(Z[c] - zo) <= 1e-9 * np.linalg.norm(zo), c
+    b = orc_m.rhs(prob.sources[0])
+    xo, it_o, _, ok = orc_m.solve(b, max_iters=2000)
+    x, it, rr, st = P.solve(prob.sources[:1], max_iters=2000)
+    x = to_np(x)[0]
+    say(f"   ORAS_MULT iters gpu={it[0]} oracle={it_o}")
+    assert ok and abs(int(it[0]) - it_o) <= 1 and rr[0] <= 1e-8
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precision", [B.MXW_FP64, B.MXW_MIXED])
+def test_tile_choices_agree(precision):
+    """Every SpMV lanes-per-row choice and both k slice widths of the
+    multi-column local solve give the same results to rounding (a ragged
+    second column chunk included); the autotuner picks among them and leaves
+    the results unchanged."""
+    prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2)
+    say(f"[gpu] tile choices precision={precision}")
+    P = Problem.from_problem(prob, precision=precision)
+    rng = np.random.default_rng(13)
+    V = rng.standard_normal((33, P.ndof)) + 1j * rng.standard_normal((33, P.ndof))
+    Vt = torch.from_numpy(V).cuda()
+    P.set_tiles(16, 8)
+    Y0, Z0 = to_np(P.apply_A(Vt)), to_np(P.apply_prec(Vt))
+    tol = 1e-12 if precision == B.MXW_FP64 else 1e-5
+    for g in (4, 8, 32):
+        P.set_tiles(spmv_group=g)
+        Y = to_np(P.apply_A(Vt))
+        assert np.linalg.norm(Y - Y0) <= 1e-14 * np.linalg.norm(Y0), g
+    P.set_tiles(multi_ku=4)
+    Z = to_np(P.apply_prec(Vt))
+    for c in range(33):
+        assert np.linalg.norm(Z[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
+    t = P.tune(nrhs=33)
+    say(f"   tuned {t}")
+    assert t["spmv_group"] in (4, 8, 16, 32) and t["multi_ku"] in (4, 8)
+    assert all(ms > 0 for ms in t["spmv_ms"]) and all(ms > 0 for ms in t["multi_ms"])
+    Z = to_np(P.apply_prec(Vt))
+    for c in range(33):
+        assert np.linalg.norm(Z[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
+    with pytest.raises(B.MxwError):
+        P.set_tiles(spmv_group=12)
+    with pytest.raises(B.MxwError):
+        P.tune(nrhs=0)

@@ -1,0 +1,172 @@
+"""Krylov subspace recycling on the GPU (GCRO-DR over a sequence of systems,
+the method Sec. 6 proposes for the slowly varying systems of the imaging
+loop) against the oracle's GCRO-DR, through the C ABI.
+
+Bars: solutions 1e-6 relative l2 and Arnoldi steps within +-1 of the oracle
+for every system of the sequence (the end-to-end bar of the plain solve);
+the recycled space the GPU keeps satisfies C^H C = I, A Ubar = C and
+M^{-1} U = Ubar to rounding, and spans the oracle's space up to the
+sensitivity of the harmonic Ritz selection."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.recycle import RecycleSpace, gcrodr
+from oracle.solve import OracleSolver
+from paper_1605_04521_amd import _lib as B
+from paper_1605_04521_amd import gen
+from paper_1605_04521_amd.api import Problem
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_with(base, eps):
+    m = base.mesh
+    return OracleSolver(m.xyz, m.tets, eps, m.bfaces, m.bface_kind, base.part, base.n_sub, base.overlap,
+                        base.k0, base.degree)
+
+
+def check_space(P, tol=1e-8):
+    U, Ub, Cm = P.recycle_space()
+    d = U.shape[0]
+    Cn = to_np(Cm)
+    assert np.linalg.norm(Cn.conj() @ Cn.T - np.eye(d)) <= 1e-10
+    AUb = to_np(P.apply_A(Ub))
+    assert np.linalg.norm(AUb - Cn) <= tol * np.sqrt(d)
+    MU = to_np(P.apply_prec(U))
+    assert np.linalg.norm(MU - to_np(Ub)) <= tol * np.linalg.norm(to_np(Ub))
+    return Cn
+
+
+def cos_angles(A, Bm):
+    qa, _ = np.linalg.qr(A.T)
+    qb, _ = np.linalg.qr(Bm.T)
+    return np.linalg.svd(qa.conj().T @ qb, compute_uv=False)
+
+
+@pytest.mark.parametrize("case", ["chamber4_r2", "cube6_r1"])
+def test_recycling_sequence_matches_oracle(case):
+    """Three systems whose media differ by 1 % (then 2 %), the last with two
+    right-hand sides: every solve against the oracle's GCRO-DR with the same
+    recycled dimension and cycle length."""
+    if case == "chamber4_r2":
+        base = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1, n_sources=2)
+    else:
+        base = gen.cube_planewave_problem(n=6, degree=1, box=3, overlap=1, n_sources=2)
+    k, m = 8, 20
+    say(f"[gpu] recycling sequence {case} k={k} m={m}")
+    sp = RecycleSpace(k)
+    P = None
+    for step in range(3):
+        eps = base.eps * (1.0 + 0.01 * step)
+        orc = oracle_with(base, eps)
+        if P is None:
+            P = Problem.from_problem(base)
+        else:
+            P.set_medium(eps)
+        nsrc = 2 if step == 2 else 1
+        srcs = base.sources[:nsrc]
+        b = P.rhs(srcs)
+        x, it, rr, _ = P.solve_recycle(b, k=k, restart=m)
+        x = to_np(x)
+        for c in range(nsrc):
+            bo = orc.rhs(srcs[c])
+            xo, ito, rro, ok = gcrodr(lambda v: orc.A @ v, orc.prec.apply, bo, sp, fresh_operator=(c == 0),
+                                      restart=m)
+            say(f"   step {step} col {c}: iters gpu={it[c]} oracle={ito} relres {rr[c]:.2e}")
+            assert ok and rr[c] <= 1e-8
+            assert abs(int(it[c]) - ito) <= 1, (step, c, it[c], ito)
+            assert np.linalg.norm(x[c] - xo) <= 1e-6 * np.linalg.norm(xo), (step, c)
+        Cn = check_space(P)
+        cs = cos_angles(Cn, sp.C.T)
+        say(f"   step {step}: cosines of the angles to the oracle's range(C): min {cs.min():.6f}")
+        assert cs.min() > 0.99
+    st = P.recycle_stats()
+    assert st["refreshes"] == 2 and st["failures"] == 0 and st["deflations"] >= 4
+
+
+def test_first_cycle_is_gmres():
+    """With no recycled space the first cycle is GMRES(m): after exactly one
+    cycle the iterate equals the plain solve's (same cycle length)."""
+    prob = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1)
+    say("[gpu] recycling: first cycle vs GMRES")
+    P = Problem.from_problem(prob)
+    b = P.rhs(prob.sources[:1])
+    x1, it1, rr1, _ = P.solve_recycle(b, k=5, restart=12, max_iters=12, allow_notconv=True)
+    x2, it2, rr2, _ = P.solve_rhs(b, restart=12, max_iters=12, allow_notconv=True)
+    assert it1[0] == it2[0] == 12
+    assert np.linalg.norm(to_np(x1) - to_np(x2)) <= 1e-10 * np.linalg.norm(to_np(x2))
+    assert abs(rr1[0] - rr2[0]) <= 1e-8 * rr2[0]
+    U, Ub, Cm = P.recycle_space()
+    assert U.shape[0] == 5
+
+
+def test_rhs_in_recycled_range_needs_no_iterations():
+    """b = A Ubar c lies in range(C): the projection that starts the solve is
+    the exact solution, with no Arnoldi step."""
+    prob = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1)
+    say("[gpu] recycling: right-hand side in range(C)")
+    P = Problem.from_problem(prob)
+    b = P.rhs(prob.sources[:1])
+    P.solve_recycle(b, k=6, restart=20)
+    U, Ub, Cm = P.recycle_space()
+    c = (torch.arange(1, 7, dtype=torch.float64) + 1j).to(torch.complex128).cuda()
+    xe = (c[:, None] * Ub).sum(0, keepdim=True)
+    b2 = P.apply_A(xe)
+    x, it, rr, _ = P.solve_recycle(b2, k=6, restart=20)
+    assert it[0] == 0 and rr[0] <= 1e-8
+    assert np.linalg.norm(to_np(x - xe)) <= 1e-8 * np.linalg.norm(to_np(xe))
+
+
+def test_reset_and_options():
+    """A reset space starts the next solve as GMRES again; invalid recycled
+    dimensions and cycle lengths are rejected."""
+    prob = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1)
+    say("[gpu] recycling: reset and options")
+    P = Problem.from_problem(prob)
+    b = P.rhs(prob.sources[:1])
+    _, it_a, _, _ = P.solve_recycle(b, k=4, restart=16)
+    _, it_b, _, _ = P.solve_recycle(b, k=4, restart=16)
+    P.recycle_reset()
+    _, it_c, _, _ = P.solve_recycle(b, k=4, restart=16)
+    assert it_c[0] == it_a[0] and it_b[0] < it_a[0]
+    for k, m in [(0, 16), (16, 16), (33, 64), (4, 65)]:
+        with pytest.raises(B.MxwError):
+            P.solve_recycle(b, k=k, restart=m)
+    Q = Problem.from_problem(prob, defer_factor=True)
+    with pytest.raises(B.MxwError):
+        Q.solve_recycle(b, k=4, restart=16)
+
+
+def test_recycling_oas_variant():
+    """The gathered partition of unity (OAS) goes through the same recycling
+    path (one-column local solves with a gather): against the oracle's OAS."""
+    prob = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1)
+    say("[gpu] recycling with OAS")
+    orc = OracleSolver.from_problem(prob, "oas")
+    P = Problem.from_problem(prob, variant=B.MXW_PREC_OAS)
+    sp = RecycleSpace(6)
+    for c in range(2):
+        src = prob.sources[:1]
+        b = P.rhs(src)
+        if c == 1:
+            b = b * (1.0 + 0.5j)
+        x, it, rr, _ = P.solve_recycle(b, k=6, restart=20)
+        bo = orc.rhs(src[0]) * (1.0 + 0.5j if c == 1 else 1.0)
+        xo, ito, _, ok = gcrodr(lambda v: orc.A @ v, orc.prec.apply, bo, sp, fresh_operator=False, restart=20)
+        say(f"   col {c}: iters gpu={it[0]} oracle={ito}")
+        assert ok and abs(int(it[0]) - ito) <= 1
+        assert np.linalg.norm(to_np(x)[0] - xo) <= 1e-6 * np.linalg.norm(xo)
+    check_space(P)
