@@ -26,6 +26,7 @@ from .mesh import DofMap, IMPEDANCE, Topology
 
 SRC_DIPOLE = 0
 SRC_PLANEWAVE = 1
+SRC_PORT = 2
 
 
 def face_geometry(topo: Topology, t: int, lf: int):
@@ -185,11 +186,12 @@ class Discretization:
     def point(self, t: int, lam):
         return lam @ self.topo.xyz[self.topo.tets[t]]
 
-    def rhs_boundary(self, gfun, q=None):
-        """b_i = int_{impedance faces} g . phi_i; gfun(x, n, beta, t) -> complex 3-vector."""
+    def rhs_boundary(self, gfun, q=None, faces=None):
+        """b_i = int_{impedance faces} g . phi_i; gfun(x, n, beta, t) -> complex 3-vector.
+        faces: a subset of imp_faces (default all)."""
         q = q if q is not None else self.basis.r + 3
         b = np.zeros(self.ndof, dtype=np.complex128)
-        for t, lf, beta in self.imp_faces:
+        for t, lf, beta in (self.imp_faces if faces is None else faces):
             pts, wts, nrm = self.face_points(t, lf, q)
             loc = np.zeros(self.basis.nloc, dtype=np.complex128)
             for lam, wq in zip(pts, wts):
@@ -244,6 +246,9 @@ class Discretization:
             return self.rhs_dipole(src.pos, src.pol)
         if src.kind == SRC_PLANEWAVE:
             return self.rhs_planewave(src.pol, src.dir)
+        if src.kind == SRC_PORT:
+            from .ports import rhs_port
+            return rhs_port(self, src)
         raise ValueError("unknown source kind")
 
     # ------------------------------------------------------------------

@@ -25,6 +25,7 @@ BC_PEC = 0
 BC_IMPEDANCE = 1
 SRC_DIPOLE = 0
 SRC_PLANEWAVE = 1
+SRC_PORT = 2
 
 # speed of light (m/s); chamber wavenumber at 1 GHz in 1/m
 C0 = 299792458.0
@@ -45,8 +46,8 @@ class Mesh:
 class Source:
     kind: int
     pos: tuple = (0.0, 0.0, 0.0)
-    pol: tuple = (0j, 0j, 0j)       # complex polarisation / dipole moment
-    dir: tuple = (0.0, 0.0, 0.0)    # plane-wave propagation direction
+    pol: tuple = (0j, 0j, 0j)       # complex polarisation / dipole moment; port: half-height vector
+    dir: tuple = (0.0, 0.0, 0.0)    # plane-wave propagation direction; port: half-width vector
 
 
 @dataclass
@@ -130,6 +131,42 @@ def unit_cube(n: int, bc: int = BC_IMPEDANCE) -> Mesh:
     bf, bk = _grid_boundary_faces(n, tets, lambda a, s: bc)
     return Mesh(xyz=xyz, tets=tets.astype(np.int32), bfaces=bf, bface_kind=bk,
                 grid_n=n, cube_of_tet=cube.astype(np.int32))
+
+
+def waveguide(n: int, a: float, b: float, length: float, cells=None) -> Mesh:
+    """Rectangular waveguide section [0,a] x [0,b] x [0,length] as a Kuhn grid
+    of n^3 cells (stretched per axis): metallic (PEC) side walls, impedance
+    faces at z = 0 and z = length (the two ports)."""
+    tets, cube = _kuhn_topology(n)
+    m = n + 1
+    g = np.arange(m) / n
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([a * x.ravel(), b * y.ravel(), length * z.ravel()], axis=1)
+    bf, bk = _grid_boundary_faces(n, tets, lambda ax, side: BC_IMPEDANCE if ax == 2 else BC_PEC)
+    return Mesh(xyz=xyz, tets=tets.astype(np.int32), bfaces=bf, bface_kind=bk,
+                grid_n=n, cube_of_tet=cube.astype(np.int32))
+
+
+def port(center, half_width, half_height) -> Source:
+    """Rectangular port: centre, half the wide side (the TE10 profile varies
+    along it) and half the narrow side (the direction of E)."""
+    return Source(kind=SRC_PORT, pos=tuple(float(v) for v in center),
+                  pol=tuple(complex(v) for v in half_height), dir=tuple(float(v) for v in half_width))
+
+
+def top_ports(count: int, radius: float = 0.15, height: float = 0.28, ring: float = 0.09,
+              width: float = 0.04, narrow: float = 0.02) -> list:
+    """count rectangular ports on the chamber's flat top (z = height), centred
+    on a ring, wide side tangential: synthetic stand-ins for the chamber's
+    waveguide ports (the real ones open into the lateral wall)."""
+    out = []
+    for q in range(count):
+        t = 2.0 * math.pi * q / count
+        c = (ring * math.cos(t), ring * math.sin(t), height)
+        hw = (-0.5 * width * math.sin(t), 0.5 * width * math.cos(t), 0.0)
+        hh = (0.5 * narrow * math.cos(t), 0.5 * narrow * math.sin(t), 0.0)
+        out.append(port(c, hw, hh))
+    return out
 
 
 def chamber_cylinder(n: int, radius: float = 0.15, height: float = 0.28, shape: str = "cylinder") -> Mesh:
