@@ -66,7 +66,9 @@ enum { MXW_BC_PEC = 0, MXW_BC_IMPEDANCE = 1 };
 /* local factor precision: FP64 everywhere, or complex-FP32 local LU/solves
  * with everything else (assembly, SpMV, Arnoldi, least squares) in FP64 */
 enum { MXW_FP64 = 0, MXW_MIXED = 1 };
-enum { MXW_SRC_DIPOLE = 0, MXW_SRC_PLANEWAVE = 1 };
+/* sources: point dipole, incident plane wave on the impedance boundary, and
+ * a rectangular waveguide port excited by its TE10 mode (eq. (3)) */
+enum { MXW_SRC_DIPOLE = 0, MXW_SRC_PLANEWAVE = 1, MXW_SRC_PORT = 2 };
 /* multi-source Krylov drivers (Sec. 5): PSEUDOBLOCK = one Krylov space per
  * right-hand side, all operations fused over the columns; BLOCK = one shared
  * block Krylov space (block CGS2 orthogonalisation, Cholesky QR of each new
@@ -102,13 +104,23 @@ typedef struct {
   int32_t reserved;
 } mxw_problem_desc;
 
+/* Port (MXW_SRC_PORT): a rectangle on the impedance boundary with centre pos,
+ * half its wide side dir (width a = 2 |dir|; the TE10 profile varies along it)
+ * and half its narrow side pol_re (height b = 2 |pol_re|; the direction v of
+ * E), dir orthogonal to pol_re, pol_im unused.  Its faces are the impedance
+ * faces whose centroid lies in the rectangle (within 1e-9 (a + b), also off
+ * its plane).  The mode on the port is E0 = sin(pi (s + a/2) / a) v, s the
+ * coordinate along dir from pos; it enters the domain with the propagation
+ * constant beta10 = sqrt(max(beta^2 - (pi/a)^2, 0)), beta the face's
+ * impedance wave number, so the port data of eq. (3) are
+ * g = -i (beta10 + beta) E0 (exp(-i w t) convention). */
 typedef struct {
   int32_t kind;               /* MXW_SRC_* */
   int32_t reserved;
-  double pos[3];              /* dipole position */
-  double pol_re[3];           /* dipole moment / plane-wave polarisation */
+  double pos[3];              /* dipole position / port centre */
+  double pol_re[3];           /* dipole moment / plane-wave polarisation / port half height */
   double pol_im[3];
-  double dir[3];              /* plane-wave unit direction */
+  double dir[3];              /* plane-wave unit direction / port half width */
 } mxw_source;
 
 typedef struct {
@@ -204,7 +216,9 @@ mxw_status mxw_problem_export_local(const mxw_problem* prob, int32_t s, double* 
 /* Right-hand sides b [nrhs][ndof] (device complex128) for the sources:
  * dipole b_i = p . phi_i(x_s) in the lowest-index element containing x_s;
  * plane wave b_i = int g . phi_i over impedance faces, g from
- * E = p exp(i k0 sqrt(eps) d.x). */
+ * E = p exp(i k0 sqrt(eps) d.x); port (eq. (3)) b_i = int g . phi_i over the
+ * port's faces, g = -i (beta10 + beta) E0 (see mxw_source).  MXW_EINVAL for
+ * an unknown kind or a malformed port. */
 mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev,
                            void* stream);
 /* y = A x for nrhs device vectors [nrhs][ndof] complex128. */
@@ -228,6 +242,16 @@ mxw_status mxw_solve(mxw_problem* prob, int32_t nrhs, const mxw_source* src,
 mxw_status mxw_solve_rhs(mxw_problem* prob, int32_t nrhs, const double* b_dev,
                          const mxw_solve_opts* opts, void* stream, double* x_dev,
                          int32_t* iters_out, double* relres_out);
+
+/* S-matrix (eq. (5)) of nsol fields X (device complex128 [nsol][ndof]) on
+ * nports ports (MXW_SRC_PORT sources): S_ij = int_{Gamma_i} conj(E_j) . E0_i
+ * / int_{Gamma_i} |E0_i|^2, the integrals taken with the right-hand sides'
+ * face quadrature; S_dev receives device complex128 [nports][nsol]
+ * (caller-allocated).  Allocates temporary device buffers and synchronises
+ * the stream.  MXW_EINVAL for a source that is not a valid port or a port
+ * with no face. */
+mxw_status mxw_smatrix(mxw_problem* prob, int32_t nports, const mxw_source* ports, int32_t nsol,
+                       const double* X_dev, void* stream, double* S_dev);
 
 /* Krylov subspace recycling (Sec. 6: GCRO-DR, the method of Parks, de Sturler
  * et al., 2006, proposed there for the slowly varying systems of the imaging

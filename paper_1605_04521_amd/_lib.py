@@ -110,6 +110,8 @@ _SIGS = {
     "mxw_solve_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "mxw_problem_tune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(Tuning)]),
     "mxw_problem_set_tiles": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "mxw_smatrix": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Source), C.c_int32, C.c_void_p, C.c_void_p,
+                                C.c_void_p]),
     "mxw_solve_recycle": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mxw_recycle_reset": (C.c_int32, [C.c_void_p]),

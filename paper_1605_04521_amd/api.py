@@ -189,6 +189,15 @@ class Problem:
         status = B.check(st, allowed)
         return x, it, rr, status
 
+    def smatrix(self, ports, X):
+        """S[i, j] (eq. (5)) of the fields X [nsol][ndof] on the ports."""
+        import torch
+        X = X.contiguous()
+        S = torch.empty((len(ports), X.shape[0]), dtype=torch.complex128, device="cuda")
+        src = B.make_sources(ports)
+        B.check(B.lib().mxw_smatrix(self.h, len(ports), src, X.shape[0], X.data_ptr(), _stream(), S.data_ptr()))
+        return S
+
     def solve_recycle(self, b, k: int = 10, tol=1e-8, restart=50, max_iters=5000, allow_notconv=False):
         """GCRO-DR solves of the columns of b one after another, with the
         problem's recycled space of k vectors carried between them (and to

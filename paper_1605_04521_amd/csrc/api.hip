@@ -525,6 +525,30 @@ void spmv_dev(mxw_problem* P, hipStream_t st, const double2* x, double2* y, cons
   launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, x, n, y, n, b, n, ncol, active);
 }
 
+// A port source: centre, unit vectors along the wide (u) and narrow (v)
+// sides, width a and height b.
+struct PortFrame {
+  double c[3], u[3], v[3], a, b;
+};
+
+mxw_status port_frame(const mxw_source& S, PortFrame& f) {
+  const double hw = std::sqrt(S.dir[0] * S.dir[0] + S.dir[1] * S.dir[1] + S.dir[2] * S.dir[2]);
+  const double hh = std::sqrt(S.pol_re[0] * S.pol_re[0] + S.pol_re[1] * S.pol_re[1] + S.pol_re[2] * S.pol_re[2]);
+  const double dot = S.dir[0] * S.pol_re[0] + S.dir[1] * S.pol_re[1] + S.dir[2] * S.pol_re[2];
+  if (S.kind != MXW_SRC_PORT || !(hw > 0) || !(hh > 0) || std::fabs(dot) > 1e-9 * hw * hh) {
+    set_error("a port needs non-zero, orthogonal half-width (dir) and half-height (pol_re) vectors");
+    return MXW_EINVAL;
+  }
+  for (int q = 0; q < 3; ++q) {
+    f.c[q] = S.pos[q];
+    f.u[q] = S.dir[q] / hw;
+    f.v[q] = S.pol_re[q] / hh;
+  }
+  f.a = 2.0 * hw;
+  f.b = 2.0 * hh;
+  return MXW_OK;
+}
+
 mxw_status check_problem(const mxw_problem* P) {
   if (!P) {
     set_error("problem is NULL");
@@ -1604,6 +1628,16 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
                        prob->imp_eps, prob->fphi, L.basis.nfloc, prob->k0, prob->nq, prob->gx, prob->gw, prob->dof_ent,
                        prob->ent_imp_ptr, prob->ent_imps, prob->ft_dofs};
       launch_rhs_planewave(st, pa, S.pol_re, S.pol_im, S.dir, work, b + (int64_t)c * n);
+    } else if (S.kind == MXW_SRC_PORT) {
+      PortFrame pf;
+      TRY(port_frame(S, pf));
+      if (!work) {
+        HIP_CHECK(hipMallocAsync((void**)&work, sizeof(double2) * std::max<size_t>(1, L.imp_ft.size() * L.basis.nfloc), st));
+      }
+      PlaneWaveArgs pa{(int)L.imp_ft.size(), n, prob->xyz, prob->ft_vert, prob->imp_ft, prob->imp_opp, prob->imp_beta,
+                       prob->imp_eps, prob->fphi, L.basis.nfloc, prob->k0, prob->nq, prob->gx, prob->gw, prob->dof_ent,
+                       prob->ent_imp_ptr, prob->ent_imps, prob->ft_dofs};
+      launch_rhs_port(st, pa, pf.c, pf.u, pf.v, pf.a, pf.b, 0, work, nullptr, nullptr, b + (int64_t)c * n);
     } else {
       set_error("unknown source kind");
       return MXW_EINVAL;
@@ -1949,6 +1983,59 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));
   if (out) *out = t;
+  return MXW_OK;
+}
+
+mxw_status mxw_smatrix(mxw_problem* P, int32_t nports, const mxw_source* ports, int32_t nsol, const double* X_dev,
+                       void* stream, double* S_dev) {
+  TRY(check_problem(P));
+  if (nports < 1 || nsol < 1 || !ports || !X_dev || !S_dev) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  std::vector<PortFrame> pf(nports);
+  for (int i = 0; i < nports; ++i) TRY(port_frame(ports[i], pf[i]));
+  hipStream_t st = (hipStream_t)stream;
+  const Layout& L = P->L;
+  const int64_t n = L.ndof;
+  const int nimp = (int)L.imp_ft.size();
+  constexpr int kChunk = 32;
+  DevMem tmp;
+  double2* W = tmp.alloc<double2>((size_t)kChunk * n);
+  double2* work = tmp.alloc<double2>(std::max<size_t>(1, (size_t)nimp * L.basis.nfloc));
+  double* fnorm = tmp.alloc<double>(std::max(1, nimp));
+  double* den = tmp.alloc<double>(kChunk);
+  double2* num = tmp.alloc<double2>((size_t)kChunk * nsol);
+  BlockWork bw;
+  if (!W || !work || !fnorm || !den || !num || ensure_block_ws(bw, n, kChunk, (nsol + kChunk - 1) / kChunk + 1) != MXW_OK) {
+    set_error("device allocation failed (S-matrix buffers)");
+    return MXW_ENOMEM;
+  }
+  PlaneWaveArgs pa{nimp, n, P->xyz, P->ft_vert, P->imp_ft, P->imp_opp, P->imp_beta, P->imp_eps, P->fphi, L.basis.nfloc,
+                   P->k0, P->nq, P->gx, P->gw, P->dof_ent, P->ent_imp_ptr, P->ent_imps, P->ft_dofs};
+  std::vector<double> dh(kChunk);
+  for (int i0 = 0; i0 < nports; i0 += kChunk) {
+    const int np = std::min(kChunk, nports - i0);
+    HIP_CHECK(hipMemsetAsync(W, 0, sizeof(double2) * np * n, st));   // the face integrals are added into W
+    for (int i = 0; i < np; ++i)
+      launch_rhs_port(st, pa, pf[i0 + i].c, pf[i0 + i].u, pf[i0 + i].v, pf[i0 + i].a, pf[i0 + i].b, 1, work, fnorm,
+                      den + i, W + (int64_t)i * n);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(dh.data(), den, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int i = 0; i < np; ++i)
+      if (!(dh[i] > 0)) {
+        std::ostringstream os;
+        os << "port " << i0 + i << " has no impedance face";
+        set_error(os.str());
+        return MXW_EINVAL;
+      }
+    // num[i nsol + j] = sum_k conj(X_j[k]) W_i[k]
+    TRY(gram(bw, n, st, (const double2*)X_dev, nsol, W, np, num));
+    launch_smatrix_finish(st, nsol, np, num, den, (double2*)S_dev + (int64_t)i0 * nsol);
+    HIP_CHECK(hipGetLastError());
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
   return MXW_OK;
 }
 

@@ -411,6 +411,103 @@ __global__ void k_rhs_planewave(int nimp, const double* __restrict__ xyz, const 
 }
 
 // b[i] += sum over the impedance faces of i's entity of their contribution.
+// Rectangular port with the TE10 mode (eq. (3), eq. (5)).  A face belongs to
+// the port when its centroid lies in the rectangle c + s u + t v, |s| <= a/2,
+// |t| <= b/2 (within 1e-9 (a + b), also off the plane).  The mode on the
+// port is E0 = sin(pi (s + a/2) / a) v.
+//   mode 0: face integrals of g . phi_p, g = -i (beta10 + beta) E0 (the
+//           excitation; beta10 = sqrt(max(beta^2 - (pi/a)^2, 0)))
+//   mode 1: face integrals of E0 . phi_p (the S-matrix weights) and, per
+//           face, the integral of |E0|^2 in fnorm
+// Faces outside the port write zeros.
+__global__ void k_rhs_port(int nimp, const double* __restrict__ xyz, const int* __restrict__ fvert,
+                           const int* __restrict__ imp_ft, const double* __restrict__ imp_beta,
+                           const Term* __restrict__ fphi, int nfloc, int nq, const double* __restrict__ gx,
+                           const double* __restrict__ gw, double c0, double c1, double c2, double u0, double u1,
+                           double u2, double v0, double v1, double v2, double aw, double bh, int mode,
+                           double2* __restrict__ out, double* __restrict__ fnorm) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nimp) return;
+  const int64_t f = imp_ft[k];
+  double Y[3][3], g[3][3], area, nrm[3];
+  for (int q = 0; q < 3; ++q)
+    for (int c = 0; c < 3; ++c) Y[q][c] = xyz[3 * (int64_t)fvert[3 * f + q] + c];
+  face_gradients(Y, g, &area, nrm);
+  const double cen[3] = {c0, c1, c2}, u[3] = {u0, u1, u2}, v[3] = {v0, v1, v2};
+  const double pn[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+  double ds = 0.0, dt = 0.0, dn = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double x = (Y[0][c] + Y[1][c] + Y[2][c]) / 3.0 - cen[c];
+    ds += x * u[c];
+    dt += x * v[c];
+    dn += x * pn[c];
+  }
+  const double tol = 1e-9 * (aw + bh);
+  const bool in = fabs(dn) <= tol && fabs(ds) <= 0.5 * aw + tol && fabs(dt) <= 0.5 * bh + tol;
+  if (!in) {
+    for (int p = 0; p < nfloc; ++p) out[(int64_t)k * nfloc + p] = make_double2(0.0, 0.0);
+    if (fnorm) fnorm[k] = 0.0;
+    return;
+  }
+  const double beta = imp_beta[k];
+  const double kc = M_PI / aw;
+  const double b10 = sqrt(fmax(beta * beta - kc * kc, 0.0));
+  // the factor multiplying E0: -i (beta10 + beta) or 1
+  const double fr = mode == 0 ? 0.0 : 1.0, fi = mode == 0 ? -(b10 + beta) : 0.0;
+  double accr[kMaxFaceLoc], acci[kMaxFaceLoc];
+  for (int p = 0; p < kMaxFaceLoc; ++p) accr[p] = acci[p] = 0.0;
+  double fn = 0.0;
+  for (int a = 0; a < nq; ++a)
+    for (int b = 0; b < nq; ++b) {
+      const double xi = gx[a], eta = gx[b];
+      const double mu[3] = {1.0 - xi, xi * (1.0 - eta), xi * eta};
+      const double w = 2.0 * area * gw[a] * gw[b] * xi;
+      double s = 0.0;
+      for (int c = 0; c < 3; ++c) s += (mu[0] * Y[0][c] + mu[1] * Y[1][c] + mu[2] * Y[2][c] - cen[c]) * u[c];
+      const double prof = sin(kc * (s + 0.5 * aw));
+      fn += w * prof * prof;
+      for (int p = 0; p < nfloc; ++p) {
+        double ph[3] = {0.0, 0.0, 0.0};
+        for (int t = 0; t < kMaxPhiTerms; ++t) {
+          const Term& tm = fphi[p * kMaxPhiTerms + t];
+          double mono = tm.coef;
+          for (int m = 0; m < 3; ++m)
+            for (int e = 0; e < tm.alpha[m]; ++e) mono *= mu[m];
+          for (int c = 0; c < 3; ++c) ph[c] += mono * g[tm.u][c];
+        }
+        const double pv = w * prof * (ph[0] * v[0] + ph[1] * v[1] + ph[2] * v[2]);
+        accr[p] += fr * pv;
+        acci[p] += fi * pv;
+      }
+    }
+  for (int p = 0; p < nfloc; ++p) out[(int64_t)k * nfloc + p] = make_double2(accr[p], acci[p]);
+  if (fnorm) fnorm[k] = fn;
+}
+
+// out[0] = sum of x[0..n) (one block, fixed order)
+__global__ void k_sum_fixed(int n, const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += x[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// S[(i0 + i) nsol + j] = num[i nsol + j] / den[i]
+__global__ void k_smatrix_finish(int nsol, int np, const double2* __restrict__ num, const double* __restrict__ den,
+                                 double2* __restrict__ S) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nsol * np) return;
+  const int i = e / nsol;
+  const double d = den[i];
+  S[e] = make_double2(num[e].x / d, num[e].y / d);
+}
+
 __global__ void k_gather_face_rhs(int64_t ndof, const int* __restrict__ dof_ent, const int64_t* __restrict__ ent_imp_ptr,
                                   const int* __restrict__ ent_imps, const int* __restrict__ imp_ft,
                                   const int* __restrict__ ft_dofs, int nfloc, const double2* __restrict__ fr,
@@ -523,6 +620,25 @@ void launch_rhs_dipole(hipStream_t st, const double* xyz, const int* tets, const
                        double2* b) {
   hipLaunchKernelGGL(k_rhs_dipole, dim3(1), dim3(64), 0, st, xyz, tets, tet_dofs, phi, nloc, t, lam[0], lam[1],
                      lam[2], lam[3], pr[0], pr[1], pr[2], pi[0], pi[1], pi[2], b);
+}
+
+void launch_rhs_port(hipStream_t st, const PlaneWaveArgs& a, const double c[3], const double u[3], const double v[3],
+                     double aw, double bh, int mode, double2* work, double* fnorm, double* den, double2* b) {
+  if (a.nimp == 0) {   // b (accumulated into) stays as it is
+    if (den) hipMemsetAsync(den, 0, sizeof(double), st);
+    return;
+  }
+  hipLaunchKernelGGL(k_rhs_port, dim3((a.nimp + 63) / 64), dim3(64), 0, st, a.nimp, a.xyz, a.fvert, a.imp_ft,
+                     a.imp_beta, a.fphi, a.nfloc, a.nq, a.gx, a.gw, c[0], c[1], c[2], u[0], u[1], u[2], v[0], v[1],
+                     v[2], aw, bh, mode, work, fnorm);
+  hipLaunchKernelGGL(k_gather_face_rhs, dim3((unsigned)((a.ndof + 255) / 256)), dim3(256), 0, st, a.ndof, a.dof_ent,
+                     a.ent_imp_ptr, a.ent_imps, a.imp_ft, a.ft_dofs, a.nfloc, work, b);
+  if (den && fnorm) hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, a.nimp, fnorm, den);
+}
+
+void launch_smatrix_finish(hipStream_t st, int nsol, int np, const double2* num, const double* den, double2* S) {
+  const int tot = nsol * np;
+  hipLaunchKernelGGL(k_smatrix_finish, dim3((tot + 255) / 256), dim3(256), 0, st, nsol, np, num, den, S);
 }
 
 void launch_rhs_planewave(hipStream_t st, const PlaneWaveArgs& a, const double pr[3], const double pi[3],

@@ -101,6 +101,12 @@ struct PlaneWaveArgs {
 };
 void launch_rhs_planewave(hipStream_t st, const PlaneWaveArgs& a, const double pr[3], const double pi[3],
                           const double d[3], double2* work, double2* b);
+// rectangular TE10 port: mode 0 excitation g (eq. (3)), mode 1 mode weights
+// and, in den, the mode's squared norm on the port (eq. (5)); the face
+// integrals are added into b
+void launch_rhs_port(hipStream_t st, const PlaneWaveArgs& a, const double c[3], const double u[3], const double v[3],
+                     double aw, double bh, int mode, double2* work, double* fnorm, double* den, double2* b);
+void launch_smatrix_finish(hipStream_t st, int nsol, int np, const double2* num, const double* den, double2* S);
 
 template <typename R>
 void launch_lu(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds, int* perm,

@@ -1,0 +1,117 @@
+"""Ports on the GPU: TE10 excitation (eq. (3)) and the S-matrix (eq. (5))
+against the oracle, through the C ABI, and the waveguide section against its
+closed-form field.
+
+Bars: port right-hand sides 1e-12 (same exact integrals, another summation
+order); the S-matrix of given fields 1e-12; S from GPU solves against S from
+oracle solves 1e-6 (the solve tolerance's bar)."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.ports import smatrix as oracle_smatrix
+from oracle.solve import OracleSolver
+from paper_1605_04521_amd import _lib as B
+from paper_1605_04521_amd import gen
+from paper_1605_04521_amd.api import Problem
+
+pytestmark = pytest.mark.gpu
+
+A_W, B_W, LEN, K0 = 1.0, 0.5, 1.5, 5.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def guide_problem(n, r):
+    mesh = gen.waveguide(n, A_W, B_W, LEN)
+    part, n_sub = gen.box_partition(mesh, max(1, n // 2))
+    ports = [gen.port((A_W / 2, B_W / 2, 0.0), (A_W / 2, 0, 0), (0, B_W / 2, 0)),
+             gen.port((A_W / 2, B_W / 2, LEN), (A_W / 2, 0, 0), (0, B_W / 2, 0))]
+    eps = np.ones(len(mesh.tets), dtype=np.complex128)
+    prob = gen.Problem(mesh=mesh, eps=eps, part=part, n_sub=n_sub, overlap=1, k0=K0, degree=r, sources=ports,
+                       name=f"waveguide n={n} r={r}")
+    return prob
+
+
+def exact_profile():
+    bt = K0
+    b10 = np.sqrt(K0 ** 2 - (np.pi / A_W) ** 2)
+    e = np.exp(1j * b10 * LEN)
+    M = np.array([[-1j * b10 - 1j * bt, 1j * b10 - 1j * bt],
+                  [(1j * b10 - 1j * bt) * e, (-1j * b10 - 1j * bt) / e]])
+    A, Bc = np.linalg.solve(M, [-1j * (b10 + bt), 0.0])
+    return lambda z: A * np.exp(1j * b10 * z) + Bc * np.exp(-1j * b10 * z)
+
+
+CASES = {
+    "guide4_r2": lambda: guide_problem(4, 2),
+    "chamber6_r2_top4": lambda: gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2),
+}
+
+
+def ports_of(name, prob):
+    return prob.sources if name.startswith("guide") else gen.top_ports(4)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_port_rhs_and_smatrix_match_oracle(name):
+    """Port right-hand sides against the oracle; the S-matrix of the same
+    (oracle-solved) fields; the S-matrix of the GPU's own solves."""
+    prob = CASES[name]()
+    ports = ports_of(name, prob)
+    say(f"[gpu] ports {name}: {len(ports)} ports")
+    orc = OracleSolver.from_problem(prob)
+    P = Problem.from_problem(prob)
+    b = to_np(P.rhs(ports))
+    Bo = np.stack([orc.rhs(p) for p in ports])
+    for i in range(len(ports)):
+        assert np.linalg.norm(b[i] - Bo[i]) <= 1e-12 * np.linalg.norm(Bo[i]), i
+    Xo = np.stack([orc.solve(Bo[i])[0] for i in range(len(ports))])
+    So = oracle_smatrix(orc.disc, Xo.T, ports)
+    S = to_np(P.smatrix(ports, torch.from_numpy(Xo).cuda()))
+    assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
+    S2 = to_np(P.smatrix(ports, torch.from_numpy(Xo).cuda()))      # reused device memory
+    assert np.array_equal(S, S2)
+    x, it, rr, _ = P.solve_rhs(torch.from_numpy(b).cuda())
+    Sg = to_np(P.smatrix(ports, x))
+    say(f"   |S| max {np.abs(So).max():.3e}, GPU-solve vs oracle-solve {np.abs(Sg - So).max():.2e}")
+    assert np.abs(Sg - So).max() <= 1e-6 * np.abs(So).max()
+
+
+def test_waveguide_closed_form_on_gpu():
+    """The whole GPU path (assembly, port excitation, ORAS-GMRES, S-matrix)
+    on the waveguide section against its exact field: S_11 = conj(f(0)),
+    S_21 = conj(f(L)), and S_12 = S_21 (reciprocity, to the solve tolerance)."""
+    prob = guide_problem(4, 2)
+    say("[gpu] waveguide section, closed form")
+    P = Problem.from_problem(prob)
+    b = P.rhs(prob.sources)
+    x, it, rr, _ = P.solve_rhs(b, tol=1e-10)
+    S = to_np(P.smatrix(prob.sources, x))
+    f = exact_profile()
+    err = max(abs(S[0, 0] - np.conj(f(0.0))), abs(S[1, 0] - np.conj(f(LEN))))
+    say(f"   S11 {S[0, 0]:.5f} S21 {S[1, 0]:.5f}; exact {np.conj(f(0.0)):.5f} {np.conj(f(LEN)):.5f}; err {err:.2e}")
+    assert err < 3e-2
+    assert abs(S[0, 1] - S[1, 0]) <= 1e-7 * abs(S[1, 0])
+
+
+def test_invalid_ports():
+    prob = guide_problem(3, 1)
+    P = Problem.from_problem(prob)
+    bad = gen.port((0.5, 0.25, 0.0), (0.5, 0, 0), (0.5, 0, 0))          # parallel sides
+    with pytest.raises(B.MxwError):
+        P.rhs([bad])
+    off = gen.port((0.5, 0.25, 0.7), (0.5, 0, 0), (0, 0.25, 0))         # no boundary face
+    x = torch.zeros((1, P.ndof), dtype=torch.complex128, device="cuda")
+    with pytest.raises(B.MxwError):
+        P.smatrix([off], x)
