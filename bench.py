@@ -147,9 +147,15 @@ def build_workload(args):
         prob = gen.chamber_problem(n=args.n, nz=args.nz, degree=args.degree, n_sub=nsub, overlap=args.overlap,
                                    seed=args.seed, n_sources=max(args.nrhs, args.nsources))
         kind = f"{args.nsub}-cell block-aligned" if "x" in args.nsub else "RCB"
+        srcs = f"{max(args.nrhs, args.nsources)} dipole(s)"
+        if args.ports:
+            width = min(0.03, 0.8 * 2.0 * np.pi * 0.1 / args.ports)   # neighbours do not overlap
+            prob.sources = gen.top_ports(args.ports, ring=0.1, width=width, narrow=0.5 * width)
+            srcs = (f"{args.ports} TE10 ports on the top ({100 * width:.2f} x {50 * width:.2f} cm, ring r = 10 cm) "
+                    f"and their S-matrix")
         wl = (f"imaging chamber cylinder R=0.15 m H=0.28 m, O-grid {args.n}x{args.n // 2}x{args.nz}, "
               f"r={args.degree}, {prob.n_sub} {kind} subdomains, {args.overlap} face layers, "
-              f"{max(args.nrhs, args.nsources)} dipole(s), eps 44+20i / head 40+15i / inclusion")
+              f"{srcs}, eps 44+20i / head 40+15i / inclusion")
     lay = Layout.from_problem(prob)
     info = lay.info()
     t_mesh = time.perf_counter() - t0
@@ -332,6 +338,8 @@ def main():
                          "Robin with the multiplicity partition of unity (ORAS_MULT)")
     ap.add_argument("--krylov", default="pseudo", choices=["pseudo", "block"],
                     help="pseudo-block (one Krylov space per source) or block GMRES (one shared space)")
+    ap.add_argument("--ports", type=int, default=0,
+                    help="excite this many synthetic TE10 ports (one solve each) and form their S-matrix per step")
     ap.add_argument("--sequence", action="store_true",
                     help="slowly varying media: step i scales eps by 1 + 0.01 i (an imaging-loop sequence)")
     ap.add_argument("--recycle", type=int, default=0,
@@ -364,6 +372,8 @@ def main():
         return
     precision = B.MXW_FP64 if args.precision == "fp64" else B.MXW_MIXED
     nsources = args.nsources if args.nsources > 0 else args.nrhs
+    if args.ports:
+        nsources = args.ports
 
     prob, lay, info, wl, t_mesh = build_workload(args)
     footprint = lay.footprint(precision, args.nrhs)
@@ -392,7 +402,7 @@ def main():
         t1 = time.perf_counter()
         krylov = B.MXW_KRYLOV_BLOCK if args.krylov == "block" else B.MXW_KRYLOV_PSEUDOBLOCK
         # all sources of the step, nrhs at a time (one block each)
-        its, rrs = [], []
+        its, rrs, xs = [], [], []
         for c0 in range(0, nsources, args.nrhs):
             if args.recycle:
                 b = P.rhs(prob.sources[c0:c0 + args.nrhs])
@@ -402,6 +412,10 @@ def main():
                                         krylov=krylov, restart=args.restart)
             its.append(it)
             rrs.append(rr)
+            if args.ports:
+                xs.append(x)
+        if args.ports:   # S-matrix of every port's field on every port (eq. (5))
+            holder["S"] = P.smatrix(prob.sources, torch.cat(xs))
         it, rr = np.concatenate(its), np.concatenate(rrs)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -467,6 +481,11 @@ def main():
         "kernels": kern,
         "tiles": tiles,
     }
+    if args.ports:
+        S = holder["S"].cpu().numpy()
+        out["smatrix"] = {"nports": args.ports, "max_abs": float(np.abs(S).max()),
+                          "reciprocity": float(np.abs(S - S.T).max() / np.abs(S).max()),
+                          "diag_mean": [float(np.mean(np.diag(S)).real), float(np.mean(np.diag(S)).imag)]}
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample (CPU)")
         out["cpu_baseline"] = cpu_baseline(prob, int(np.median(iters)))
