@@ -1969,13 +1969,11 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
       return MXW_ENOMEM;
     }
     const int kus[2] = {4, 8};
-    int bk = 1;
     for (int q = 0; q < 2; ++q) {
       P->multi_ku = kus[q];
       t.multi_ms[q] = time_ms([&] { apply_prec_dev(P, st, x, n, y, n, nrhs, nullptr, nullptr, xbuf); });
-      if (t.multi_ms[q] < t.multi_ms[bk]) bk = q;
     }
-    P->multi_ku = kus[bk];
+    P->multi_ku = t.multi_ms[0] < t.multi_ms[1] ? kus[0] : kus[1];
   }
   t.multi_ku = P->multi_ku;
   hipEventDestroy(ea);

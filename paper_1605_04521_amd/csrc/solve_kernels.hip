@@ -229,11 +229,29 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t* __restri
   const double2* xc = x + (int64_t)col * xstride;
   double sr = 0.0, si = 0.0;
   const int64_t r0 = rowptr[row], r1 = rowptr[row + 1];
-  for (int64_t c = r0 + l; c < r1; c += G) {
-    const double2 a = vals[c];
-    const double2 xv = xc[cols[c]];
-    sr += a.x * xv.x - a.y * xv.y;
-    si += a.x * xv.y + a.y * xv.x;
+  // a lane's entries c, c + G, c + 2G, ... summed in that order; four of them
+  // are loaded together (indices and values first, then the x gathers) so
+  // that a row's loads are in flight at once
+  for (int64_t c = r0 + l; c < r1; c += 4 * G) {
+    int ci[4];
+    double2 a[4], xv[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = c + u * G;
+      ok[u] = e < r1;
+      ci[u] = ok[u] ? cols[e] : 0;
+      a[u] = ok[u] ? vals[e] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = xc[ci[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (ok[u]) {
+        sr += a[u].x * xv[u].x - a[u].y * xv[u].y;
+        si += a[u].x * xv[u].y + a[u].y * xv[u].x;
+      }
+    }
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) {

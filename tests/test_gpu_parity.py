@@ -407,6 +407,9 @@ def test_tile_choices_agree(precision):
     say(f"   tuned {t}")
     assert t["spmv_group"] in (4, 8, 16, 32) and t["multi_ku"] in (4, 8)
     assert all(ms > 0 for ms in t["spmv_ms"]) and all(ms > 0 for ms in t["multi_ms"])
+    # the fastest of each is kept
+    assert t["spmv_ms"][(4, 8, 16, 32).index(t["spmv_group"])] == min(t["spmv_ms"])
+    assert t["multi_ms"][(4, 8).index(t["multi_ku"])] == min(t["multi_ms"])
     Z = to_np(P.apply_prec(Vt))
     for c in range(33):
         assert np.linalg.norm(Z[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c

@@ -170,3 +170,30 @@ def test_recycling_oas_variant():
         assert ok and abs(int(it[0]) - ito) <= 1
         assert np.linalg.norm(to_np(x)[0] - xo) <= 1e-6 * np.linalg.norm(xo)
     check_space(P)
+
+
+def test_recycling_mixed_precision():
+    """FP32 local factors (the precision of the batched path) under the FP64
+    GCRO-DR: every system of a 1 %-varying sequence reaches the tolerance and
+    the E-field agrees with the FP64 oracle's GCRO-DR to 1e-5 (the mixed
+    path's stated error), with at most 3 more Arnoldi steps."""
+    base = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1)
+    k, m = 8, 20
+    say("[gpu] recycling sequence, FP32 local factors")
+    sp = RecycleSpace(k)
+    P = None
+    for step in range(3):
+        eps = base.eps * (1.0 + 0.01 * step)
+        orc = oracle_with(base, eps)
+        if P is None:
+            P = Problem.from_problem(base, precision=B.MXW_MIXED)
+        else:
+            P.set_medium(eps)
+        b = P.rhs(base.sources[:1])
+        x, it, rr, _ = P.solve_recycle(b, k=k, restart=m)
+        bo = orc.rhs(base.sources[0])
+        xo, ito, _, ok = gcrodr(lambda v: orc.A @ v, orc.prec.apply, bo, sp, restart=m)
+        err = np.linalg.norm(to_np(x)[0] - xo) / np.linalg.norm(xo)
+        say(f"   step {step}: iters gpu={it[0]} oracle={ito} relres {rr[0]:.2e} E err {err:.2e}")
+        assert ok and rr[0] <= 1e-8 and err <= 1e-5
+        assert int(it[0]) <= ito + 3
