@@ -48,9 +48,8 @@ struct PanelSmem {
 
 template <typename R, int NB>
 struct SweepSmem {
-  R Tr[2 * NB][NB + 1], Ti[2 * NB][NB + 1];        // T of the 64-row pass
-  R Br[3][NB][NB + 1], Bi[3][NB][NB + 1];          // first diagonal inverse, coupling block, second diagonal inverse
-  R Yr[NB][NB + 1], Yi[NB][NB + 1];                // solution of the first block
+  R Tr[2 * NB][NB + 1], Ti[2 * NB][NB + 1];        // T of the 64-row pass, overwritten by its solution
+  R Br[2][NB][NB + 1], Bi[2][NB][NB + 1];          // [0] first, then second diagonal inverse; [1] coupling block
 };
 
 template <typename R, int NB>
@@ -82,7 +81,7 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
                                     R* __restrict__ Ai, __amdgpu_buffer_rsrc_t fr, __amdgpu_buffer_rsrc_t fi,
                                     R* __restrict__ Xr, R* __restrict__ Xi, __amdgpu_buffer_rsrc_t xrr,
                                     __amdgpu_buffer_rsrc_t xir) {
-  constexpr int PC = NB, SB = 2 * NB, KU = 8;
+  constexpr int PC = NB, SB = 2 * NB, KU = sizeof(R) == 8 ? 4 : 8;
   typedef typename Mfma<R>::acc_t acc_t;
   const int wave = threadIdx.x >> 6;
   const int rh = wave & 1, kh = wave >> 1;
@@ -154,8 +153,13 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
             vr = c < r ? vr : (c == r && r < bn ? R(1) : R(0));
             vi = c < r ? vi : R(0);
           }
-          sm.Br[m][r][c] = vr;
-          sm.Bi[m][r][c] = vi;
+          if (m < 2) {
+            sm.Br[m][r][c] = vr;
+            sm.Bi[m][r][c] = vi;
+          } else {   // kept in registers until the first block is solved
+            pbr[2][j] = vr;
+            pbi[2][j] = vi;
+          }
         }
       }
     }
@@ -176,22 +180,29 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
       __syncthreads();
     }
     if (solve0) {
-      // Y0 = M0 T0 -> Y; T1 -= C Y0; Y1 = M1 T1 -> rows NB.. of T
+      // Y0 = M0 T0 -> rows 0.. of T; T1 -= C Y0; Y1 = M1 T1 -> rows NB.. of T
       const int orow = (wave & 1) * 16, ocol = (wave >> 1) * 16 + li;
       {
         acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
         tile_product<R, NB, PC>(sm.Br[0], sm.Bi[0], sm.Tr, sm.Ti, lane, wave, yre, yim);
+        __syncthreads();   // every wave has read T0 and M0 before they are overwritten
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = orow + Mfma<R>::row(lane, q);
-          sm.Yr[r][ocol] = yre[q];
-          sm.Yi[r][ocol] = yim[q];
+          sm.Tr[r][ocol] = yre[q];
+          sm.Ti[r][ocol] = yim[q];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {   // the second diagonal inverse takes M0's place
+          const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+          sm.Br[0][r][c] = pbr[2][j];
+          sm.Bi[0][r][c] = pbi[2][j];
         }
       }
       __syncthreads();
       if (n1 > 0) {
         acc_t cre = acc_t{0, 0, 0, 0}, cim = acc_t{0, 0, 0, 0};
-        tile_product<R, NB, PC>(sm.Br[1], sm.Bi[1], sm.Yr, sm.Yi, lane, wave, cre, cim);
+        tile_product<R, NB, PC>(sm.Br[1], sm.Bi[1], sm.Tr, sm.Ti, lane, wave, cre, cim);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = orow + Mfma<R>::row(lane, q);
@@ -200,7 +211,7 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
         }
         __syncthreads();
         acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
-        tile_product<R, NB, PC>(sm.Br[2], sm.Bi[2], sm.Tr + NB, sm.Ti + NB, lane, wave, yre, yim);
+        tile_product<R, NB, PC>(sm.Br[0], sm.Bi[0], sm.Tr + NB, sm.Ti + NB, lane, wave, yre, yim);
         __syncthreads();   // every wave has read T1 before it is overwritten by Y1
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -208,13 +219,6 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
           sm.Tr[NB + r][ocol] = yre[q];
           sm.Ti[NB + r][ocol] = yim[q];
         }
-      }
-      // rows r0..r0+32 of the result to Tr as well (from Y)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
-        sm.Tr[r][c] = sm.Yr[r][c];
-        sm.Ti[r][c] = sm.Yi[r][c];
       }
       __syncthreads();
       // rows left of j0 to the row-major scratch (operand of later passes)
@@ -242,12 +246,15 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
 }
 
 template <typename R, int NB>
-__global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __restrict__ foff,
+__global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t* __restrict__ foff,
                                             const int* __restrict__ nsz, const int* __restrict__ lds,
                                             int* __restrict__ perm, const int64_t* __restrict__ poff,
                                             R* __restrict__ xscr, int* __restrict__ info,
                                             const int* __restrict__ order) {
   static_assert(NB == 32, "the sweep tiles assume 32-wide blocks");
+  // panel columns updated together per row (fewer in FP64, whose registers
+  // are twice as wide)
+  constexpr int HC = sizeof(R) == 8 ? 8 : 16;
   __shared__ LuSmem<R, NB> smu;
   PanelSmem<R, NB>& sm = smu.p;
   const int s = order ? order[blockIdx.x] : blockIdx.x;
@@ -362,14 +369,14 @@ __global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __
           BufStore<R>::at(fi, oj[t], lim[t]);
         }
 #pragma nounroll
-        for (int h = 0; h < NB; h += 16) {
-          if (h + 16 <= jj + 1 || h >= kb) continue;   // uniform: no live column in this half
-          R xr[2][16], xi[2][16];
-          int off[2][16];
+        for (int h = 0; h < NB; h += HC) {
+          if (h + HC <= jj + 1 || h >= kb) continue;   // uniform: no live column in this part
+          R xr[2][HC], xi[2][HC];
+          int off[2][HC];
 #pragma unroll
           for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < HC; ++u) {
               const int c = h + u;
               off[t][u] = (c > jj && c < kb && row[t] < n) ? ((k + c) * (int)ld + row[t]) * (int)sizeof(R) : kOob;
               xr[t][u] = BufLoad<R>::at(fr, off[t][u]);
@@ -378,7 +385,7 @@ __global__ void __launch_bounds__(256) k_lu(R* __restrict__ F, const int64_t* __
 #pragma unroll
           for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < HC; ++u) {
               const R pr_ = sm.ur[h + u], pi_ = sm.ui[h + u];
               xr[t][u] -= lr[t] * pr_ - lim[t] * pi_;
               xi[t][u] -= lr[t] * pi_ + lim[t] * pr_;
