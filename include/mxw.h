@@ -296,23 +296,32 @@ typedef struct {
   double spmv_ms[4];          /* time per SpMV launch with 4, 8, 16, 32 lanes per row */
   double multi_ms[2];         /* time per multi-column local solve with 4-, 8-wide k
                                  slices (0 where not measured) */
+  int32_t lu_ku;              /* k slice width of the LU's block-column update (FP64: always 4) */
+  int32_t reserved;
+  double lu_ms[2];            /* time per LU of every A_s with 4-, 8-wide k slices (FP32
+                                 factors only; 0 where not measured) */
 } mxw_tuning;
 
 /* Autotuner (launch mechanics; not a passage of the paper): times the SpMV
- * on nrhs columns with 4, 8, 16 and 32 lanes per row and, for nrhs >= 2, a
+ * on nrhs columns with 4, 8, 16 and 32 lanes per row; for nrhs >= 2, a
  * Boolean partition of unity (ORAS, RAS) and a factorised problem, the
- * multi-column local solve with 4- and 8-wide k slices, on this problem's own
- * operator and factors; later calls on the problem use the fastest of each.
- * Results do not depend on the choice beyond rounding.  Allocates temporary
+ * multi-column local solve with 4- and 8-wide k slices; and for FP32 factors
+ * (MXW_MIXED, factorised) the LU with 4- and 8-wide k slices (each trial
+ * re-assembles the local matrices and factorises them again: seconds at a
+ * million unknowns; the problem ends factorised with the fastest), all on
+ * this problem's own operator and factors; later calls on the problem use
+ * the fastest of each.  Results do not depend on the choice beyond rounding
+ * (a re-factorisation makes recycled spaces stale).  Allocates temporary
  * device buffers (2 nrhs ndof complex128, plus the multi-column scratch) and
  * synchronises the stream.  out may be NULL.  MXW_EINVAL for nrhs outside
  * 1..4096. */
 mxw_status mxw_problem_tune(mxw_problem* prob, int32_t nrhs, void* stream, mxw_tuning* out);
 
 /* Sets the tile choices by hand (for instance those a previous
- * mxw_problem_tune call picked): spmv_group in {4, 8, 16, 32}, multi_ku in
- * {4, 8}; 0 leaves a choice unchanged.  MXW_EINVAL for other values. */
-mxw_status mxw_problem_set_tiles(mxw_problem* prob, int32_t spmv_group, int32_t multi_ku);
+ * mxw_problem_tune call picked): spmv_group in {4, 8, 16, 32}, multi_ku and
+ * lu_ku in {4, 8} (lu_ku applies to the next factorisation, FP32 only); 0
+ * leaves a choice unchanged.  MXW_EINVAL for other values. */
+mxw_status mxw_problem_set_tiles(mxw_problem* prob, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku);
 
 /* Residual estimates |g_{j+1}| / ||b|| of every Arnoldi step of column col
  * in the last solve on this problem (host array; len receives the count,

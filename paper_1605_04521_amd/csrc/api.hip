@@ -313,6 +313,7 @@ struct mxw_problem {
   bool mixed = false;
   int spmv_group = 16;
   int multi_ku = 8;       // k slice width of the multi-column local solve (tunable)
+  int lu_ku = 8;          // k slice width of the LU's block-column update (tunable in FP32)
   uint64_t op_gen = 0;    // bumped whenever A or M changes (recycled spaces go stale)
   KrylovWork kw;
   BlockWork bw;
@@ -575,7 +576,7 @@ mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor) {
   if (factor) {
     ScopedKernelTimer tm("lu");
     launch_lu<R>(st, L.n_sub, (R*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (R*)P->lu_scratch, P->info,
-                 P->order);
+                 P->order, P->lu_ku);
   }
   HIP_CHECK(hipGetLastError());
   return MXW_OK;
@@ -588,11 +589,11 @@ mxw_status factor_impl(mxw_problem* P, hipStream_t st) {
     (void)NB;
     ScopedKernelTimer tm("lu");
     launch_lu<float>(st, P->L.n_sub, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (float*)P->lu_scratch,
-                     P->info, P->order);
+                     P->info, P->order, P->lu_ku);
   } else {
     ScopedKernelTimer tm("lu");
     launch_lu<double>(st, P->L.n_sub, (double*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
-                      (double*)P->lu_scratch, P->info, P->order);
+                      (double*)P->lu_scratch, P->info, P->order, P->lu_ku);
   }
   HIP_CHECK(hipGetLastError());
   std::vector<int> info(P->L.n_sub);
@@ -1904,16 +1905,18 @@ mxw_status mxw_solve(mxw_problem* P, int32_t nrhs, const mxw_source* src, const 
   return s;
 }
 
-mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t multi_ku) {
+mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku) {
   TRY(check_problem(P));
   const bool g_ok = spmv_group == 0 || spmv_group == 4 || spmv_group == 8 || spmv_group == 16 || spmv_group == 32;
   const bool k_ok = multi_ku == 0 || multi_ku == 4 || multi_ku == 8;
-  if (!g_ok || !k_ok) {
-    set_error("spmv_group must be 0, 4, 8, 16 or 32 and multi_ku 0, 4 or 8");
+  const bool l_ok = lu_ku == 0 || lu_ku == 4 || lu_ku == 8;
+  if (!g_ok || !k_ok || !l_ok) {
+    set_error("spmv_group must be 0, 4, 8, 16 or 32, multi_ku and lu_ku 0, 4 or 8");
     return MXW_EINVAL;
   }
   if (spmv_group) P->spmv_group = spmv_group;
   if (multi_ku) P->multi_ku = multi_ku;
+  if (lu_ku) P->lu_ku = lu_ku;
   return MXW_OK;
 }
 
@@ -1976,6 +1979,32 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
     P->multi_ku = t.multi_ms[0] < t.multi_ms[1] ? kus[0] : kus[1];
   }
   t.multi_ku = P->multi_ku;
+  if (P->mixed && P->factored) {
+    // the LU is in place: each trial re-assembles the local matrices first
+    const int kus[2] = {4, 8};
+    for (int q = 0; q < 2; ++q) {
+      P->lu_ku = kus[q];
+      TRY(build_local_and_factor<float>(P, st, false));
+      hipEventRecord(ea, st);
+      launch_lu<float>(st, P->L.n_sub, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
+                       (float*)P->lu_scratch, P->info, P->order, P->lu_ku);
+      hipEventRecord(eb, st);
+      hipEventSynchronize(eb);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ea, eb);
+      t.lu_ms[q] = ms;
+    }
+    const int best = t.lu_ms[0] < t.lu_ms[1] ? kus[0] : kus[1];
+    if (best != P->lu_ku) {
+      P->lu_ku = best;
+      P->factored = false;
+      TRY(build_local_and_factor<float>(P, st, false));
+      TRY(factor_impl(P, st));
+    } else {
+      ++P->op_gen;   // new factors (same operator up to rounding)
+    }
+  }
+  t.lu_ku = P->mixed ? P->lu_ku : 4;
   hipEventDestroy(ea);
   hipEventDestroy(eb);
   HIP_CHECK(hipGetLastError());

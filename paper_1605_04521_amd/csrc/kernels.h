@@ -110,7 +110,7 @@ void launch_smatrix_finish(hipStream_t st, int nsol, int np, const double2* num,
 
 template <typename R>
 void launch_lu(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds, int* perm,
-               const int64_t* poff, R* scratch, int* info, const int* order);
+               const int64_t* poff, R* scratch, int* info, const int* order, int ku);
 
 struct LocalSolveArgs {
   int n_sub;

@@ -76,12 +76,12 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // factored part, applies the triangular blocks where the rows are left of j0,
 // and writes the result back to the factor storage and, for rows left of j0
 // (the only rows later passes use as operand), to the row-major scratch X.
-template <typename R, int NB>
+template <typename R, int NB, int KU>
 __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0, int kb, R* __restrict__ Ar,
                                     R* __restrict__ Ai, __amdgpu_buffer_rsrc_t fr, __amdgpu_buffer_rsrc_t fi,
                                     R* __restrict__ Xr, R* __restrict__ Xi, __amdgpu_buffer_rsrc_t xrr,
                                     __amdgpu_buffer_rsrc_t xir) {
-  constexpr int PC = NB, SB = 2 * NB, KU = sizeof(R) == 8 ? 4 : 8;
+  constexpr int PC = NB, SB = 2 * NB;
   typedef typename Mfma<R>::acc_t acc_t;
   const int wave = threadIdx.x >> 6;
   const int rh = wave & 1, kh = wave >> 1;
@@ -245,7 +245,7 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
   }
 }
 
-template <typename R, int NB>
+template <typename R, int NB, int KU>
 __global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t* __restrict__ foff,
                                             const int* __restrict__ nsz, const int* __restrict__ lds,
                                             int* __restrict__ perm, const int64_t* __restrict__ poff,
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t*
   for (int k = 0; k < n; k += NB) {
     const int kb = min(NB, n - k);
     // ---- A-C. bring the block column up to date with the factored part
-    if (k > 0) update_block_column<R, NB>(smu.s, n, (int)ld, k, kb, Ar, Ai, fr, fi, Xr, Xi, xrr, xir);
+    if (k > 0) update_block_column<R, NB, KU>(smu.s, n, (int)ld, k, kb, Ar, Ai, fr, fi, Xr, Xi, xrr, xir);
     // ---- 1. panel factorisation; (best, bi): this thread's candidate pivot
     double best = -1.0;
     int bi = 0x7fffffff;
@@ -530,16 +530,22 @@ __global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t*
   if (tid == 0) info[s] = first_zero;
 }
 
+// ku: k slice width of the block-column update (4 or 8); FP64 always takes 4
+// (8 would spill at two workgroups per CU)
 template <typename R>
 void launch_lu(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds, int* perm,
-               const int64_t* poff, R* scratch, int* info, const int* order) {
-  if (n_sub > 0)
-    timed_launch(k_lu<R, kLuNB>, dim3(n_sub), dim3(256), 0, st, F, foff, nsz, lds, perm, poff, scratch, info,
+               const int64_t* poff, R* scratch, int* info, const int* order, int ku) {
+  if (n_sub <= 0) return;
+  if (sizeof(R) == 8 || ku == 4)
+    timed_launch(k_lu<R, kLuNB, 4>, dim3(n_sub), dim3(256), 0, st, F, foff, nsz, lds, perm, poff, scratch, info,
+                 order);
+  else
+    timed_launch(k_lu<R, kLuNB, 8>, dim3(n_sub), dim3(256), 0, st, F, foff, nsz, lds, perm, poff, scratch, info,
                  order);
 }
 template void launch_lu<double>(hipStream_t, int, double*, const int64_t*, const int*, const int*, int*,
-                                const int64_t*, double*, int*, const int*);
+                                const int64_t*, double*, int*, const int*, int);
 template void launch_lu<float>(hipStream_t, int, float*, const int64_t*, const int*, const int*, int*,
-                               const int64_t*, float*, int*, const int*);
+                               const int64_t*, float*, int*, const int*, int);
 
 }  // namespace mxw

@@ -413,7 +413,18 @@ def test_tile_choices_agree(precision):
     Z = to_np(P.apply_prec(Vt))
     for c in range(33):
         assert np.linalg.norm(Z[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
+    if precision == B.MXW_MIXED:
+        assert t["lu_ms"][(4, 8).index(t["lu_ku"])] == min(t["lu_ms"]) and min(t["lu_ms"]) > 0
+    # both k slice widths of the LU (FP32 factors; FP64 always takes 4)
+    Q = Problem.from_problem(prob, precision=precision, defer_factor=True)
+    Q.set_tiles(lu_ku=4)
+    Q.factor()
+    Zq = to_np(Q.apply_prec(Vt))
+    for c in range(33):
+        assert np.linalg.norm(Zq[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
     with pytest.raises(B.MxwError):
         P.set_tiles(spmv_group=12)
+    with pytest.raises(B.MxwError):
+        P.set_tiles(lu_ku=6)
     with pytest.raises(B.MxwError):
         P.tune(nrhs=0)
