@@ -1936,9 +1936,16 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
     return MXW_ENOMEM;
   }
   HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double2) * n * nrhs, st));
-  hipEvent_t ea = nullptr, eb = nullptr;
-  HIP_CHECK(hipEventCreate(&ea));
-  HIP_CHECK(hipEventCreate(&eb));
+  struct Events {   // destroyed on every return path
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) hipEventDestroy(a);
+      if (b) hipEventDestroy(b);
+    }
+  } ev;
+  HIP_CHECK(hipEventCreate(&ev.a));
+  HIP_CHECK(hipEventCreate(&ev.b));
+  hipEvent_t ea = ev.a, eb = ev.b;
   // average of 3 launches after one untimed launch
   auto time_ms = [&](const std::function<void()>& fn) -> double {
     fn();
@@ -1966,8 +1973,6 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
     void* xbuf = tmp.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() *
                                           (P->mixed ? 4 : 8));
     if (!xbuf) {
-      hipEventDestroy(ea);
-      hipEventDestroy(eb);
       set_error("device allocation failed (tuning scratch)");
       return MXW_ENOMEM;
     }
@@ -2005,8 +2010,6 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
     }
   }
   t.lu_ku = P->mixed ? P->lu_ku : 4;
-  hipEventDestroy(ea);
-  hipEventDestroy(eb);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));
   if (out) *out = t;
