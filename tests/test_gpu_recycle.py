@@ -197,3 +197,28 @@ def test_recycling_mixed_precision():
         say(f"   step {step}: iters gpu={it[0]} oracle={ito} relres {rr[0]:.2e} E err {err:.2e}")
         assert ok and rr[0] <= 1e-8 and err <= 1e-5
         assert int(it[0]) <= ito + 3
+
+
+def test_recycling_largest_cycle():
+    """The largest cycle the deflated-restart kernel takes (k = 32 recycled
+    vectors, 64 vectors per cycle): two systems against the oracle."""
+    base = gen.cube_planewave_problem(n=6, degree=1, box=3, overlap=1)
+    k, m = 32, 64
+    say(f"[gpu] recycling, largest cycle k={k} m={m}")
+    sp = RecycleSpace(k)
+    P = Problem.from_problem(base)
+    for step in range(2):
+        eps = base.eps * (1.0 + 0.01 * step)
+        orc = oracle_with(base, eps)
+        if step:
+            P.set_medium(eps)
+        b = P.rhs(base.sources[:1])
+        x, it, rr, _ = P.solve_recycle(b, k=k, restart=m)
+        bo = orc.rhs(base.sources[0])
+        xo, ito, _, ok = gcrodr(lambda v: orc.A @ v, orc.prec.apply, bo, sp, restart=m)
+        say(f"   step {step}: iters gpu={it[0]} oracle={ito}")
+        assert ok and rr[0] <= 1e-8 and abs(int(it[0]) - ito) <= 1
+        assert np.linalg.norm(to_np(x)[0] - xo) <= 1e-6 * np.linalg.norm(xo)
+    check_space(P)
+    assert P.recycle_space()[0].shape[0] == k
+    assert P.recycle_stats()["failures"] == 0
