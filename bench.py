@@ -344,6 +344,9 @@ def main():
                     help="slowly varying media: step i scales eps by 1 + 0.01 i (an imaging-loop sequence)")
     ap.add_argument("--recycle", type=int, default=0,
                     help="solve with GCRO-DR, recycling a space of this many vectors from system to system")
+    ap.add_argument("--e-error", action="store_true",
+                    help="mixed precision: after the timed steps, solve the last step's sources again with FP64 "
+                         "factors and report each source's relative E-field difference")
     ap.add_argument("--tune", action="store_true",
                     help="after the warm-up, time the tile choices on the problem and keep the fastest")
     ap.add_argument("--graph", action="store_true",
@@ -412,10 +415,12 @@ def main():
                                         krylov=krylov, restart=args.restart)
             its.append(it)
             rrs.append(rr)
-            if args.ports:
+            if args.ports or args.e_error:
                 xs.append(x)
         if args.ports:   # S-matrix of every port's field on every port (eq. (5))
             holder["S"] = P.smatrix(prob.sources, torch.cat(xs))
+        if args.e_error:
+            holder["X"], holder["eps"] = torch.cat(xs), eps
         it, rr = np.concatenate(its), np.concatenate(rrs)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -481,6 +486,30 @@ def main():
         "kernels": kern,
         "tiles": tiles,
     }
+    if args.e_error and precision == B.MXW_MIXED:
+        # the same sources with FP64 factors (untimed; the mixed problem is
+        # released first so that both sets of factors never share the HBM)
+        Xm = holder.pop("X")
+        torch.cuda.synchronize()
+        log(f"[bench] device memory free before releasing the mixed problem: {torch.cuda.mem_get_info()[0] / 1e9:.1f} GB")
+        holder.pop("P").close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free, total = torch.cuda.mem_get_info()
+        log(f"[bench] device memory free for the FP64 factors: {free / 1e9:.1f} of {total / 1e9:.1f} GB "
+            f"(needed {lay.footprint(B.MXW_FP64, args.nrhs) / 1e9:.1f} GB)")
+        P64 = Problem.from_layout(lay, eps=holder["eps"], k0=prob.k0, precision=B.MXW_FP64)
+        errs = []
+        for c0 in range(0, nsources, args.nrhs):
+            kr = B.MXW_KRYLOV_BLOCK if args.krylov == "block" else B.MXW_KRYLOV_PSEUDOBLOCK
+            x64, _, _, _ = P64.solve(prob.sources[c0:c0 + args.nrhs], krylov=kr, restart=args.restart)
+            d = torch.linalg.vector_norm(Xm[c0:c0 + args.nrhs] - x64, dim=1)
+            errs += (d / torch.linalg.vector_norm(x64, dim=1)).tolist()
+        P64.close()
+        out["e_error_vs_fp64"] = {"per_source": errs, "max": max(errs),
+                                  "note": "relative l2 difference of E between FP32 and FP64 local factors, "
+                                          "both solved to a true relative residual of 1e-8"}
+        log(f"[bench] E-field difference mixed vs FP64 factors: max {max(errs):.2e}")
     if args.ports:
         S = holder["S"].cpu().numpy()
         out["smatrix"] = {"nports": args.ports, "max_abs": float(np.abs(S).max()),

@@ -115,6 +115,20 @@ struct ScopedKernelTimer {
   }
 };
 
+static void flush_timing();
+
+// Recorded timing events keep the launches they were recorded with alive in
+// the runtime, and with them the device buffers those launches used: a freed
+// buffer is only returned once they go.  Before a problem releases its memory
+// the pending records are folded into the totals and the pooled events
+// destroyed (new ones are created on demand).
+static void release_timing_events() {
+  flush_timing();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (hipEvent_t e : g_event_pool) hipEventDestroy(e);
+  g_event_pool.clear();
+}
+
 static void flush_timing() {
   std::lock_guard<std::mutex> lk(g_tmu);
   for (auto& r : g_pending) {
@@ -1507,6 +1521,7 @@ mxw_status mxw_problem_set_medium(mxw_problem* prob, const double* eps, double k
 
 void mxw_problem_destroy(mxw_problem* prob) {
   if (!prob) return;
+  release_timing_events();   // waits only on recorded timing events, if any
   if (prob->kw.host) hipHostFree(prob->kw.host);
   delete prob;
 }
