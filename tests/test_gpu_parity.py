@@ -428,3 +428,28 @@ def test_tile_choices_agree(precision):
         P.set_tiles(lu_ku=6)
     with pytest.raises(B.MxwError):
         P.tune(nrhs=0)
+
+
+def test_close_releases_device_memory_with_timing_on():
+    """A closed problem returns its device memory also while kernel timing is
+    on (recorded timing events must not keep its buffers alive)."""
+    from paper_1605_04521_amd.api import reset_timing, timing
+    prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2, n_sources=4)
+    say("[gpu] close with timing on")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    P = Problem.from_problem(prob, precision=B.MXW_MIXED)
+    timing(True)
+    reset_timing()
+    try:
+        P.solve(prob.sources, krylov=B.MXW_KRYLOV_BLOCK)
+        torch.cuda.synchronize()
+        used = free0 - torch.cuda.mem_get_info()[0]
+        P.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        left = free0 - torch.cuda.mem_get_info()[0]
+    finally:
+        timing(False)
+    say(f"   in use with the problem {used / 1e6:.0f} MB, after close {left / 1e6:.0f} MB")
+    assert used > 100e6 and left < 0.1 * used
