@@ -86,6 +86,11 @@ def test_port_rhs_and_smatrix_match_oracle(name):
     Sg = to_np(P.smatrix(ports, x))
     say(f"   |S| max {np.abs(So).max():.3e}, GPU-solve vs oracle-solve {np.abs(Sg - So).max():.2e}")
     assert np.abs(Sg - So).max() <= 1e-6 * np.abs(So).max()
+    # the ports' sources solved together (block GMRES, one Krylov space)
+    xb, itb, rrb, _ = P.solve_rhs(torch.from_numpy(b).cuda(), krylov=B.MXW_KRYLOV_BLOCK)
+    Sb = to_np(P.smatrix(ports, xb))
+    say(f"   block solve: {itb[0]} block steps, vs oracle-solve {np.abs(Sb - So).max():.2e}")
+    assert np.all(rrb <= 1e-8) and np.abs(Sb - So).max() <= 1e-6 * np.abs(So).max()
 
 
 def test_waveguide_closed_form_on_gpu():

@@ -150,13 +150,18 @@ def test_reset_and_options():
         Q.solve_recycle(b, k=4, restart=16)
 
 
-def test_recycling_oas_variant():
-    """The gathered partition of unity (OAS) goes through the same recycling
-    path (one-column local solves with a gather): against the oracle's OAS."""
+VARIANTS = {"oas": B.MXW_PREC_OAS, "ras": B.MXW_PREC_RAS, "oras_mult": B.MXW_PREC_ORAS_MULT}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_recycling_oas_variant(variant):
+    """The other Schwarz variants go through the same recycling path (OAS and
+    the multiplicity partition of unity: one-column local solves with a
+    gather; RAS: local matrices from the CSR): against the oracle's variant."""
     prob = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1)
-    say("[gpu] recycling with OAS")
-    orc = OracleSolver.from_problem(prob, "oas")
-    P = Problem.from_problem(prob, variant=B.MXW_PREC_OAS)
+    say(f"[gpu] recycling with {variant}")
+    orc = OracleSolver.from_problem(prob, variant)
+    P = Problem.from_problem(prob, variant=VARIANTS[variant])
     sp = RecycleSpace(6)
     for c in range(2):
         src = prob.sources[:1]
