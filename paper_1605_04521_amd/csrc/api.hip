@@ -653,7 +653,11 @@ mxw_status mxw_layout_create(const mxw_problem_desc* desc, mxw_layout** out) {
   return MXW_OK;
 }
 
-void mxw_layout_destroy(mxw_layout* layout) { delete layout; }
+void mxw_layout_destroy(mxw_layout* layout) {
+  if (!layout) return;
+  release_timing_events();   // the device mirror may go with the last reference
+  delete layout;
+}
 
 static void fill_info(const Layout& L, mxw_layout_info* info) {
   info->ndof = L.ndof;
