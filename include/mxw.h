@@ -297,9 +297,11 @@ typedef struct {
   double multi_ms[2];         /* time per multi-column local solve with 4-, 8-wide k
                                  slices (0 where not measured) */
   int32_t lu_ku;              /* k slice width of the LU's block-column update (FP64: always 4) */
-  int32_t reserved;
+  int32_t multi_rows;         /* rows per pass of the multi-column local solve (64 or 128) */
   double lu_ms[2];            /* time per LU of every A_s with 4-, 8-wide k slices (FP32
                                  factors only; 0 where not measured) */
+  double multi_tall_ms;       /* time per multi-column local solve with 128-row passes
+                                 (FP32 factors only; 0 where not measured) */
 } mxw_tuning;
 
 /* Autotuner (launch mechanics; not a passage of the paper): times the SpMV
@@ -319,9 +321,11 @@ mxw_status mxw_problem_tune(mxw_problem* prob, int32_t nrhs, void* stream, mxw_t
 
 /* Sets the tile choices by hand (for instance those a previous
  * mxw_problem_tune call picked): spmv_group in {4, 8, 16, 32}, multi_ku and
- * lu_ku in {4, 8} (lu_ku applies to the next factorisation, FP32 only); 0
- * leaves a choice unchanged.  MXW_EINVAL for other values. */
-mxw_status mxw_problem_set_tiles(mxw_problem* prob, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku);
+ * lu_ku in {4, 8} (lu_ku applies to the next factorisation, FP32 only),
+ * multi_rows in {64, 128} (128-row passes take 8-wide slices); 0 leaves a
+ * choice unchanged.  MXW_EINVAL for other values. */
+mxw_status mxw_problem_set_tiles(mxw_problem* prob, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku,
+                                 int32_t multi_rows);
 
 /* Residual estimates |g_{j+1}| / ||b|| of every Arnoldi step of column col
  * in the last solve on this problem (host array; len receives the count,

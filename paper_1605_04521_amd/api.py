@@ -239,10 +239,11 @@ class Problem:
         t = B.Tuning()
         B.check(B.lib().mxw_problem_tune(self.h, nrhs, _stream(), C.byref(t)))
         return {"spmv_group": t.spmv_group, "multi_ku": t.multi_ku, "spmv_ms": list(t.spmv_ms),
-                "multi_ms": list(t.multi_ms), "lu_ku": t.lu_ku, "lu_ms": list(t.lu_ms)}
+                "multi_ms": list(t.multi_ms), "lu_ku": t.lu_ku, "lu_ms": list(t.lu_ms),
+                "multi_rows": t.multi_rows, "multi_tall_ms": t.multi_tall_ms}
 
-    def set_tiles(self, spmv_group: int = 0, multi_ku: int = 0, lu_ku: int = 0):
-        B.check(B.lib().mxw_problem_set_tiles(self.h, spmv_group, multi_ku, lu_ku))
+    def set_tiles(self, spmv_group: int = 0, multi_ku: int = 0, lu_ku: int = 0, multi_rows: int = 0):
+        B.check(B.lib().mxw_problem_set_tiles(self.h, spmv_group, multi_ku, lu_ku, multi_rows))
 
     def history(self, col: int = 0) -> np.ndarray:
         """Relative residual estimates of every Arnoldi step of the last solve."""

@@ -328,6 +328,7 @@ struct mxw_problem {
   int spmv_group = 16;
   int multi_ku = 8;       // k slice width of the multi-column local solve (tunable)
   int lu_ku = 8;          // k slice width of the LU's block-column update (tunable in FP32)
+  int multi_rows = 64;    // rows per pass of the multi-column local solve (64, or 128 in FP32; tunable)
   uint64_t op_gen = 0;    // bumped whenever A or M changes (recycled spaces go stale)
   KrylovWork kw;
   BlockWork bw;
@@ -511,10 +512,10 @@ void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vs
                      P->order};
     if (P->mixed)
       launch_local_solve_multi<float>(st, a, (const float*)P->F, v, vstride, z, zstride, (float*)xbuf, P->L.sum_ns,
-                                      ncol, active, P->multi_ku);
+                                      ncol, active, P->multi_ku, P->multi_rows);
     else
       launch_local_solve_multi<double>(st, a, (const double*)P->F, v, vstride, z, zstride, (double*)xbuf,
-                                       P->L.sum_ns, ncol, active, P->multi_ku);
+                                       P->L.sum_ns, ncol, active, P->multi_ku, P->multi_rows);
     return;
   }
   ScopedKernelTimer tm("local_solve");
@@ -932,6 +933,7 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
   P->variant = variant;
   P->k0 = k0;
   P->mixed = mixed;
+  P->multi_rows = mixed ? 128 : 64;   // measured faster in FP32; in FP64 the LDS of 128 rows halves occupancy
   // views of the shared mirror
   P->xyz = S->xyz;
   P->tets = S->tets;
@@ -1924,18 +1926,22 @@ mxw_status mxw_solve(mxw_problem* P, int32_t nrhs, const mxw_source* src, const 
   return s;
 }
 
-mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku) {
+mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku,
+                                 int32_t multi_rows) {
   TRY(check_problem(P));
   const bool g_ok = spmv_group == 0 || spmv_group == 4 || spmv_group == 8 || spmv_group == 16 || spmv_group == 32;
   const bool k_ok = multi_ku == 0 || multi_ku == 4 || multi_ku == 8;
   const bool l_ok = lu_ku == 0 || lu_ku == 4 || lu_ku == 8;
-  if (!g_ok || !k_ok || !l_ok) {
-    set_error("spmv_group must be 0, 4, 8, 16 or 32, multi_ku and lu_ku 0, 4 or 8");
+  const bool r_ok = multi_rows == 0 || multi_rows == 64 || multi_rows == 128;
+  if (!g_ok || !k_ok || !l_ok || !r_ok) {
+    set_error("spmv_group must be 0, 4, 8, 16 or 32, multi_ku and lu_ku 0, 4 or 8, multi_rows 0, 64 or 128");
     return MXW_EINVAL;
   }
   if (spmv_group) P->spmv_group = spmv_group;
   if (multi_ku) P->multi_ku = multi_ku;
   if (lu_ku) P->lu_ku = lu_ku;
+  if (multi_rows) P->multi_rows = multi_rows;
+  if (P->multi_rows == 128) P->multi_ku = 8;   // 128-row passes take 8-wide slices
   return MXW_OK;
 }
 
@@ -1996,13 +2002,27 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
       return MXW_ENOMEM;
     }
     const int kus[2] = {4, 8};
+    P->multi_rows = 64;
     for (int q = 0; q < 2; ++q) {
       P->multi_ku = kus[q];
       t.multi_ms[q] = time_ms([&] { apply_prec_dev(P, st, x, n, y, n, nrhs, nullptr, nullptr, xbuf); });
     }
     P->multi_ku = t.multi_ms[0] < t.multi_ms[1] ? kus[0] : kus[1];
+    if (P->mixed) {   // 128-row passes (8-wide slices; FP32 only: in FP64 the LDS leaves one workgroup per CU)
+      P->multi_rows = 128;
+      const int ku_keep = P->multi_ku;
+      P->multi_ku = 8;
+      t.multi_tall_ms = time_ms([&] { apply_prec_dev(P, st, x, n, y, n, nrhs, nullptr, nullptr, xbuf); });
+      if (t.multi_tall_ms < std::min(t.multi_ms[0], t.multi_ms[1])) {
+        P->multi_ku = 8;
+      } else {
+        P->multi_rows = 64;
+        P->multi_ku = ku_keep;
+      }
+    }
   }
   t.multi_ku = P->multi_ku;
+  t.multi_rows = P->multi_rows;
   if (P->mixed && P->factored) {
     // the LU is in place: each trial re-assembles the local matrices first
     const int kus[2] = {4, 8};

@@ -132,7 +132,7 @@ hipError_t prepare_local_solve(size_t dyn_bytes_double, size_t dyn_bytes_float);
 template <typename R>
 void launch_local_solve_multi(hipStream_t st, const LocalSolveArgs& a, const R* F, const double2* v, int64_t vstride,
                               double2* z, int64_t zstride, R* xbuf, int64_t sum_ns, int ncol, const int* active,
-                              int ku);
+                              int ku, int rows);
 int multi_chunk_cols();
 void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const int64_t* pos, const double2* ys,
                        int64_t ystride, double2* z, int64_t zstride, int ncol, const int* active,

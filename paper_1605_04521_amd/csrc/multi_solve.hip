@@ -223,15 +223,279 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
   }
 }
 
+// The same sweeps with 128-row passes: the long product of a pass covers 128
+// rows (each wave 32 rows over the whole K range), so X is re-read once per
+// 128 factor rows instead of once per 64.  The pass is then solved as two
+// 64-row halves in solve order; the second half first takes the product with
+// the first half's new solutions (K = those 64 rows, read back from X), then
+// the same three-block triangular step.  LDS: the 128-row T block, the
+// diagonal inverse and coupling blocks (the second diagonal inverse waits in
+// registers for the first one's slot); solutions overwrite their T rows.
+template <typename R, int NB, int PC, int KU>
+__global__ void __launch_bounds__(256, 3) k_local_solve_multi_tall(
+    const R* __restrict__ F, const int64_t* __restrict__ foff, const int* __restrict__ nsz,
+    const int* __restrict__ lds, const int* __restrict__ perm, const int64_t* __restrict__ poff,
+    const int* __restrict__ sub_dofs, const uint8_t* __restrict__ pou, const double2* __restrict__ v, int64_t vstride,
+    double2* __restrict__ z, int64_t zstride, R* __restrict__ xbuf, int64_t xchunk, int ncol,
+    const int* __restrict__ active, const int* __restrict__ order) {
+  static_assert(NB == 32 && PC == 32, "tile shape assumes 32 x 32 blocks");
+  constexpr int SB = 4 * NB, HB = 2 * NB;   // rows per pass, rows per half
+  typedef typename Mfma<R>::acc_t acc_t;
+  __shared__ R Tr[SB][PC + 1], Ti[SB][PC + 1];
+  __shared__ R Br[2][NB][NB + 1], Bi[2][NB][NB + 1];   // [0] diagonal inverse, [1] coupling block
+  const int s = order ? order[blockIdx.x] : blockIdx.x;
+  const int chunk = blockIdx.y, c0 = chunk * PC;
+  const int n = nsz[s];
+  const int64_t ld = lds[s];
+  const R* Ar = F + foff[s];
+  const R* Ai = Ar + ld * n;
+  const int* P = perm + poff[s];
+  const int* D = sub_dofs + poff[s];
+  R* Xr = xbuf + (int64_t)chunk * xchunk + 2 * poff[s] * PC;
+  R* Xi = Xr + (int64_t)n * PC;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const __amdgpu_buffer_rsrc_t fr = plane_rsrc(Ar, ld * n * (int64_t)sizeof(R));
+  const __amdgpu_buffer_rsrc_t fi = plane_rsrc(Ai, ld * n * (int64_t)sizeof(R));
+  const __amdgpu_buffer_rsrc_t xrr = plane_rsrc(Xr, (int64_t)n * PC * sizeof(R));
+  const __amdgpu_buffer_rsrc_t xir = plane_rsrc(Xi, (int64_t)n * PC * sizeof(R));
+
+  // restrict and permute: X = P_s R_s v
+  for (int base = tid; base < n * PC; base += 4 * 256) {
+    double2 a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * 256;
+      a[u] = make_double2(0.0, 0.0);
+      if (idx < n * PC) {
+        const int i = idx / PC, col = c0 + idx % PC;
+        if (col < ncol) a[u] = v[(int64_t)col * vstride + D[P[i]]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * 256;
+      if (idx < n * PC) {
+        Xr[idx] = (R)a[u].x;
+        Xi[idx] = (R)a[u].y;
+      }
+    }
+  }
+  __syncthreads();
+
+  const int nsb = (n + SB - 1) / SB;
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    for (int sq = 0; sq < nsb; ++sq) {
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      const int lane = tid & 63, li = lane & 15, lk = lane >> 4;
+      const int sb = sweep == 0 ? sq : nsb - 1 - sq;
+      const int r0 = sb * SB, rn = min(SB, n - r0);
+      // the long product: wave w forms rows w*32.. of the pass over the whole
+      // K range ([0, r0) forward, [r0 + rn, n) backward)
+      const int k_lo = sweep == 0 ? 0 : r0 + rn, k_hi = sweep == 0 ? r0 : n;
+      {
+        acc_t pre[2][2], pim[2][2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            pre[rt][ct] = acc_t{0, 0, 0, 0};
+            pim[rt][ct] = acc_t{0, 0, 0, 0};
+          }
+        bool row_ok[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) row_ok[rt] = wave * NB + rt * 16 + li < rn;
+        const int arow = r0 + wave * NB + li;
+        for (int k0 = k_lo; k0 < k_hi; k0 += 4 * KU) {
+          Slice<R, KU, PC> sl;
+          sl.load(fr, fi, xrr, xir, (int)ld, arow, row_ok, k0, k_hi, lk, li);
+          __builtin_amdgcn_sched_barrier(0);
+          sl.product(pre, pim);
+        }
+        // T = X rows of the pass - product (each wave its own rows)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int idx = tid + 256 * j, r = idx / PC, c = idx % PC;
+          const int o = r < rn ? (r0 * PC + idx) * (int)sizeof(R) : kOob;
+          Tr[r][c] = BufLoad<R>::at(xrr, o);
+          Ti[r][c] = BufLoad<R>::at(xir, o);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = wave * NB + rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
+              Tr[r][c] -= pre[rt][ct][q];
+              Ti[r][c] -= pim[rt][ct][q];
+            }
+        __syncthreads();
+      }
+      for (int half = 0; half < 2; ++half) {
+        const int hb = sweep == 0 ? half : 1 - half;   // the half solved now (0: rows 0..63 of the pass)
+        const int h0 = hb * HB, hn = min(HB, rn - h0);
+        if (hn <= 0) continue;
+        const int rh = wave & 1, kh = wave >> 1;
+        if (half == 1) {
+          // the other half's rows are solved (in X): T_h -= F[h rows, other rows] X_other
+          const int o0 = (1 - hb) * HB, on = min(HB, rn - o0);
+          const int klo = r0 + o0, khi = r0 + o0 + on;
+          acc_t cre[2][2], cim[2][2];
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+              cre[rt][ct] = acc_t{0, 0, 0, 0};
+              cim[rt][ct] = acc_t{0, 0, 0, 0};
+            }
+          bool row_ok[2];
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) row_ok[rt] = rh * NB + rt * 16 + li < hn;
+          const int arow = r0 + h0 + rh * NB + li;
+          for (int k0 = klo + 4 * KU * kh; k0 < khi; k0 += 8 * KU) {
+            Slice<R, KU, PC> sl;
+            sl.load(fr, fi, xrr, xir, (int)ld, arow, row_ok, k0, khi, lk, li);
+            __builtin_amdgcn_sched_barrier(0);
+            sl.product(cre, cim);
+          }
+          for (int phase = 1; phase >= 0; --phase) {
+            if (kh == phase) {
+#pragma unroll
+              for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                  for (int q = 0; q < 4; ++q) {
+                    const int r = h0 + rh * NB + rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
+                    Tr[r][c] -= cre[rt][ct][q];
+                    Ti[r][c] -= cim[rt][ct][q];
+                  }
+            }
+            __syncthreads();
+          }
+        }
+        // three-block triangular step of the half: blocks bf then bs (forward
+        // 0 then 1, backward 1 then 0) within the half
+        const int bf = sweep == 0 ? 0 : 1, bs = 1 - bf;
+        const int nf = max(0, min(NB, hn - bf * NB)), ns = max(0, min(NB, hn - bs * NB));
+        const int hr = r0 + h0;   // first row of the half in the matrix
+        R pbr[3][4], pbi[3][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+          const int rows[3] = {bf, bs, bs}, cols[3] = {bf, bf, bs};
+          const int rlim[3] = {nf, ns, ns}, clim[3] = {nf, nf, ns};
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            const bool in = r < rlim[m] && c < clim[m];
+            const int o = in ? ((hr + cols[m] * NB + c) * (int)ld + hr + rows[m] * NB + r) * (int)sizeof(R) : kOob;
+            R vr = BufLoad<R>::at(fr, o), vi = BufLoad<R>::at(fi, o);
+            if (m != 1) {
+              const int bn = m == 0 ? nf : ns;
+              const bool keep = sweep == 0 ? c < r : c >= r;
+              vr = keep ? vr : (sweep == 0 && c == r && r < bn ? R(1) : R(0));
+              vi = keep ? vi : R(0);
+            }
+            pbr[m][j] = vr;
+            pbi[m][j] = vi;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+          Br[0][r][c] = pbr[0][j];
+          Bi[0][r][c] = pbi[0][j];
+          Br[1][r][c] = pbr[1][j];
+          Bi[1][r][c] = pbi[1][j];
+        }
+        __syncthreads();
+        const int orow = (wave & 1) * 16, ocol = (wave >> 1) * 16 + li;
+        R (*Tf)[PC + 1] = Tr + h0 + bf * NB;
+        R (*Tfi)[PC + 1] = Ti + h0 + bf * NB;
+        R (*Ts)[PC + 1] = Tr + h0 + bs * NB;
+        R (*Tsi)[PC + 1] = Ti + h0 + bs * NB;
+        if (nf > 0) {
+          acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+          tile_product<R, NB, PC>(Br[0], Bi[0], Tf, Tfi, lane, wave, yre, yim);
+          __syncthreads();   // every wave has read T_f and M_f
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = orow + Mfma<R>::row(lane, q);
+            Tf[r][ocol] = yre[q];
+            Tfi[r][ocol] = yim[q];
+            if (r < nf) {
+              Xr[(int64_t)(hr + bf * NB + r) * PC + ocol] = yre[q];
+              Xi[(int64_t)(hr + bf * NB + r) * PC + ocol] = yim[q];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {   // the second diagonal inverse takes M_f's place
+            const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+            Br[0][r][c] = pbr[2][j];
+            Bi[0][r][c] = pbi[2][j];
+          }
+          __syncthreads();
+          if (ns > 0) {
+            acc_t cre = acc_t{0, 0, 0, 0}, cim = acc_t{0, 0, 0, 0};
+            tile_product<R, NB, PC>(Br[1], Bi[1], Tf, Tfi, lane, wave, cre, cim);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = orow + Mfma<R>::row(lane, q);
+              Ts[r][ocol] -= cre[q];
+              Tsi[r][ocol] -= cim[q];
+            }
+            __syncthreads();
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int idx = tid + 256 * j, r = idx % NB, c = idx / NB;
+            Br[0][r][c] = pbr[2][j];
+            Bi[0][r][c] = pbi[2][j];
+          }
+          __syncthreads();
+        }
+        if (ns > 0) {
+          acc_t yre = acc_t{0, 0, 0, 0}, yim = acc_t{0, 0, 0, 0};
+          tile_product<R, NB, PC>(Br[0], Bi[0], Ts, Tsi, lane, wave, yre, yim);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = orow + Mfma<R>::row(lane, q);
+            if (r < ns) {
+              Xr[(int64_t)(hr + bs * NB + r) * PC + ocol] = yre[q];
+              Xi[(int64_t)(hr + bs * NB + r) * PC + ocol] = yim[q];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const uint8_t* w = pou + poff[s];
+  for (int idx = tid; idx < n * PC; idx += 256) {
+    const int i = idx / PC, c = idx % PC, col = c0 + c;
+    if (col >= ncol || !w[i]) continue;
+    if (active && !active[col]) continue;
+    z[(int64_t)col * zstride + D[i]] = make_double2((double)Xr[idx], (double)Xi[idx]);
+  }
+}
+
 template <typename R>
 void launch_local_solve_multi(hipStream_t st, const LocalSolveArgs& a, const R* F, const double2* v, int64_t vstride,
                               double2* z, int64_t zstride, R* xbuf, int64_t sum_ns, int ncol, const int* active,
-                              int ku) {
+                              int ku, int rows) {
   if (a.n_sub == 0 || ncol == 0) return;
   const int nchunk = (ncol + kMultiPC - 1) / kMultiPC;
   const int64_t xchunk = 2 * sum_ns * kMultiPC;
-  // ku: 4-wide k steps per K slice of the long product (a tuning choice)
-  if (ku == 4)
+  // ku: 4-wide k steps per K slice of the long product; rows: rows per pass
+  // over the factor (64, or 128 with 8-wide slices) -- tuning choices
+  if (rows == 128)
+    timed_launch(k_local_solve_multi_tall<R, kLuNB, kMultiPC, 8>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F,
+                 a.foff, a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol,
+                 active, a.order);
+  else if (ku == 4)
     timed_launch(k_local_solve_multi<R, kLuNB, kMultiPC, 4>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F, a.foff,
                  a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol, active,
                  a.order);
@@ -241,9 +505,11 @@ void launch_local_solve_multi(hipStream_t st, const LocalSolveArgs& a, const R* 
                  a.order);
 }
 template void launch_local_solve_multi<double>(hipStream_t, const LocalSolveArgs&, const double*, const double2*,
-                                               int64_t, double2*, int64_t, double*, int64_t, int, const int*, int);
+                                               int64_t, double2*, int64_t, double*, int64_t, int, const int*, int,
+                                               int);
 template void launch_local_solve_multi<float>(hipStream_t, const LocalSolveArgs&, const float*, const double2*,
-                                              int64_t, double2*, int64_t, float*, int64_t, int, const int*, int);
+                                              int64_t, double2*, int64_t, float*, int64_t, int, const int*, int,
+                                              int);
 
 int multi_chunk_cols() { return kMultiPC; }
 

@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # kernel key -> (name pattern, source file)
 KERNELS = {
     "lu": (r"k_lu<", "lu_kernels.hip"),
-    "local_solve_multi": (r"k_local_solve_multi<", "multi_solve.hip"),
+    "local_solve_multi": (r"k_local_solve_multi(_tall)?<", "multi_solve.hip"),
     "local_solve": (r"k_local_solve<", "solve_kernels.hip"),
     "spmv": (r"k_sp(mv|mm)<", "solve_kernels.hip"),
 }

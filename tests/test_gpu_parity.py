@@ -392,7 +392,7 @@ def test_tile_choices_agree(precision):
     rng = np.random.default_rng(13)
     V = rng.standard_normal((33, P.ndof)) + 1j * rng.standard_normal((33, P.ndof))
     Vt = torch.from_numpy(V).cuda()
-    P.set_tiles(16, 8)
+    P.set_tiles(16, 8, 0, 64)
     Y0, Z0 = to_np(P.apply_A(Vt)), to_np(P.apply_prec(Vt))
     tol = 1e-12 if precision == B.MXW_FP64 else 1e-5
     for g in (4, 8, 32):
@@ -403,18 +403,27 @@ def test_tile_choices_agree(precision):
     Z = to_np(P.apply_prec(Vt))
     for c in range(33):
         assert np.linalg.norm(Z[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
+    P.set_tiles(multi_rows=128)          # 128-row passes (ragged last pass and chunk included)
+    Z = to_np(P.apply_prec(Vt))
+    for c in range(33):
+        assert np.linalg.norm(Z[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
+    P.set_tiles(multi_rows=64, multi_ku=8)
     t = P.tune(nrhs=33)
     say(f"   tuned {t}")
     assert t["spmv_group"] in (4, 8, 16, 32) and t["multi_ku"] in (4, 8)
     assert all(ms > 0 for ms in t["spmv_ms"]) and all(ms > 0 for ms in t["multi_ms"])
     # the fastest of each is kept
     assert t["spmv_ms"][(4, 8, 16, 32).index(t["spmv_group"])] == min(t["spmv_ms"])
-    assert t["multi_ms"][(4, 8).index(t["multi_ku"])] == min(t["multi_ms"])
+    if t["multi_rows"] == 64:
+        assert t["multi_ms"][(4, 8).index(t["multi_ku"])] == min(t["multi_ms"])
     Z = to_np(P.apply_prec(Vt))
     for c in range(33):
         assert np.linalg.norm(Z[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
     if precision == B.MXW_MIXED:
         assert t["lu_ms"][(4, 8).index(t["lu_ku"])] == min(t["lu_ms"]) and min(t["lu_ms"]) > 0
+        assert t["multi_tall_ms"] > 0 and t["multi_rows"] in (64, 128)
+        if t["multi_rows"] == 128:
+            assert t["multi_tall_ms"] <= min(t["multi_ms"])
     # both k slice widths of the LU (FP32 factors; FP64 always takes 4)
     Q = Problem.from_problem(prob, precision=precision, defer_factor=True)
     Q.set_tiles(lu_ku=4)
@@ -426,6 +435,8 @@ def test_tile_choices_agree(precision):
         P.set_tiles(spmv_group=12)
     with pytest.raises(B.MxwError):
         P.set_tiles(lu_ku=6)
+    with pytest.raises(B.MxwError):
+        P.set_tiles(multi_rows=96)
     with pytest.raises(B.MxwError):
         P.tune(nrhs=0)
 
