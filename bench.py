@@ -354,8 +354,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
-                                   "is described in DESIGN.md, not implemented)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the solver runs on one GPU: --gpus must be 1 (sharding over several "
+                                   "GPUs is not implemented)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
