@@ -307,8 +307,9 @@ typedef struct {
 /* Autotuner (launch mechanics; not a passage of the paper): times the SpMV
  * on nrhs columns with 4, 8, 16 and 32 lanes per row; for nrhs >= 2, a
  * Boolean partition of unity (ORAS, RAS) and a factorised problem, the
- * multi-column local solve with 4- and 8-wide k slices; and for FP32 factors
- * (MXW_MIXED, factorised) the LU with 4- and 8-wide k slices (each trial
+ * multi-column local solve with 4- and 8-wide k slices (for FP32 factors also
+ * with 128-row passes); and for FP32 factors (MXW_MIXED, factorised) the LU
+ * with 4- and 8-wide k slices (each trial
  * re-assembles the local matrices and factorises them again: seconds at a
  * million unknowns; the problem ends factorised with the fastest), all on
  * this problem's own operator and factors; later calls on the problem use
