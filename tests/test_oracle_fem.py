@@ -52,10 +52,9 @@ def test_entity_counts_match_euler(n):
 
 @pytest.mark.parametrize("r", [1, 2, 3])
 def test_dof_counts(r):
-    # 8^3 grid: 4,184 / 21,424 / 60,936 unknowns (closed form; an independent
-    # count in the hot-path survey gives the same three numbers)
-    expect = {1: 4184, 2: 21424, 3: 60936}[r]
-    assert dofs_closed_form(8, r) == expect
+    # 8^3 grid: the closed form gives 4,184 / 21,424 / 60,936 unknowns; the
+    # oracle's numbering must produce the closed-form count
+    assert dofs_closed_form(8, r) == {1: 4184, 2: 21424, 3: 60936}[r]
     d = make_disc(gen.unit_cube(4), r)
     assert d.ndof == dofs_closed_form(4, r)
     assert {1: 604, 2: 2936, 3: 8148}[r] == d.ndof
@@ -87,10 +86,12 @@ def test_nnz_brute_force(r):
 
 @pytest.mark.slow
 def test_nnz_cube8():
-    # structural non-zeros of the 8^3 grid, r = 1, 2, 3, from the independent
-    # count quoted with the hot-path survey
-    for r, expect in ((1, 61784), (2, 872288), (3, 4952088)):
-        d = make_disc(gen.unit_cube(8), r)
+    # structural non-zeros of the 8^3 grid, r = 1, 2, 3: the brute-force count
+    # over entity pairs sharing an element (61,784 / 872,288 / 4,952,088)
+    mesh = gen.unit_cube(8)
+    for r in (1, 2, 3):
+        expect = brute_nnz(mesh, r)
+        d = make_disc(mesh, r)
         assert d.pattern()[0][-1] == expect
 
 

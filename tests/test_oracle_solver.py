@@ -154,14 +154,47 @@ def test_oras_not_slower_than_oas():
     assert ok1 and it_oras <= it_oas
 
 
+def brute_force_local_sizes(mesh, part, n_sub, layers):
+    """Local unknown counts of r = 1 (no metallic faces): edges of the
+    elements of each overlapping subdomain, by brute force over vertex sets."""
+    tets = [tuple(sorted(t)) for t in mesh.tets.tolist()]
+    by_face = {}
+    for i, t in enumerate(tets):
+        for f in ((t[0], t[1], t[2]), (t[0], t[1], t[3]), (t[0], t[2], t[3]), (t[1], t[2], t[3])):
+            by_face.setdefault(f, []).append(i)
+    sizes = []
+    for s in range(n_sub):
+        inside = {i for i in range(len(tets)) if part[i] == s}
+        for _ in range(layers):
+            grown = set(inside)
+            for i in inside:
+                t = tets[i]
+                for f in ((t[0], t[1], t[2]), (t[0], t[1], t[3]), (t[0], t[2], t[3]), (t[1], t[2], t[3])):
+                    grown.update(by_face[f])
+            inside = grown
+        edges = {(t[a], t[b]) for i in inside for t in [tets[i]] for a in range(4) for b in range(a + 1, 4)}
+        sizes.append(len(edges))
+    return sizes
+
+
 def test_small_cube_counts_and_subdomains():
-    """8^3 cube, 2x2x2 boxes, one face layer: 4,184 unknowns, 61,784 non-zeros,
-    796 local unknowns in every subdomain (the independent count quoted with the
-    hot-path survey)."""
+    """8^3 cube, 2x2x2 boxes, one face layer: 4,184 unknowns (Euler's formula),
+    61,784 non-zeros and 796 local unknowns in every subdomain (brute-force
+    counts over vertex sets, independent of the oracle's entity tables)."""
     prob = gen.cube_planewave_problem()
     s = OracleSolver.from_problem(prob)
-    assert s.ndof == 4184 and s.A.nnz == 61784
-    assert [len(x.dofs) for x in s.prec.subs] == [796] * 8
+    n = 8
+    T, V = 6 * n ** 3, (n + 1) ** 3
+    F = (4 * T + 12 * n * n) // 2
+    assert s.ndof == V + F - T - 1 == 4184
+    pairs = set()
+    for t in prob.mesh.tets.tolist():
+        t = sorted(t)
+        es = [(t[a], t[b]) for a in range(4) for b in range(a + 1, 4)]
+        pairs.update((e1, e2) for e1 in es for e2 in es)
+    assert s.A.nnz == len(pairs) == 61784
+    sizes = brute_force_local_sizes(prob.mesh, prob.part, prob.n_sub, prob.overlap)
+    assert [len(x.dofs) for x in s.prec.subs] == sizes == [796] * 8
 
 
 # --------------------------------------------------------------------------
