@@ -150,8 +150,11 @@ class ORAS:
         return sub.pou.astype(np.float64)
 
     def apply(self, v):
-        z = np.zeros(len(v), dtype=np.complex128)
+        """z = M^{-1} v; v is one vector [n] or several columns [n, k] (the
+        columns are handed to each local solve together)."""
+        z = np.zeros(v.shape, dtype=np.complex128)
         for sub in self.subs:
             y = sub.lu.solve(np.asarray(v[sub.dofs], dtype=np.complex128))
-            z[sub.dofs] += self.weights(sub) * y
+            w = self.weights(sub)
+            z[sub.dofs] += w[:, None] * y if y.ndim == 2 else w * y
         return z

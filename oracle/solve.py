@@ -42,5 +42,5 @@ class OracleSolver:
 
     def solve_block(self, B, tol=1e-8, restart=50, max_iters=5000):
         mv = lambda V: self.A @ V
-        pc = lambda V: np.stack([self.prec.apply(V[:, c]) for c in range(V.shape[1])], axis=1)
+        pc = self.prec.apply
         return block_fgmres(mv, pc, B, tol, restart, max_iters)
