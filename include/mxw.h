@@ -146,9 +146,44 @@ typedef struct {
 
 typedef struct mxw_layout mxw_layout;
 typedef struct mxw_problem mxw_problem;
+typedef struct mxw_ctx mxw_ctx;
+typedef struct mxw_ticket mxw_ticket;
+
+/* Device memory provider of a context: alloc returns a device pointer of at
+ * least `bytes` bytes on the context's device for use on `stream` (NULL on
+ * failure); free_ returns it.  Both may be called from the library's worker
+ * threads (asynchronous solves).  The library only returns memory once the
+ * work that used it is finished (it synchronises first), so a stream-ordered
+ * caching allocator such as PyTorch's may hand it out again at once. */
+typedef void* (*mxw_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*mxw_free_fn)(void* ptr, void* user);
 
 /* Message of the last failing call on this thread (never NULL). */
 const char* mxw_last_error(void);
+
+/* ---- contexts: device memory and HBM budget ----------------------------- */
+
+/* A context owns the device-memory policy of the problems created with it
+ * (the serving loop of an imaging inversion admits forward solves by their
+ * device footprint, Sec. 5-6): every device allocation those problems make
+ * (their operator and factors, the layout device copy they build, Krylov
+ * workspaces and the temporaries of a solve) goes through alloc/free_ and is
+ * counted; an allocation that would take the bytes in use above hbm_budget
+ * (0 = no limit) fails with MXW_ENOMEM before anything is allocated.  alloc =
+ * free_ = NULL: hipMalloc / hipFree.  device: the HIP device the problems
+ * live on (made current by the library's worker threads).  A problem created
+ * with ctx = NULL uses a process-wide default context (hipMalloc, no budget),
+ * whose counters mxw_ctx_usage(NULL, ...) reports. */
+mxw_status mxw_ctx_create(int32_t device, uint64_t hbm_budget, mxw_alloc_fn alloc, mxw_free_fn free_,
+                          void* user, mxw_ctx** out);
+/* Releases the context.  MXW_EBUSY (and nothing released) while device
+ * memory obtained through it is still held (live problems, or layout device
+ * copies they built); NULL is a no-op. */
+mxw_status mxw_ctx_destroy(mxw_ctx* ctx);
+/* Bytes in use now, the peak since creation (or the last reset_peak != 0
+ * call, which sets it to the bytes in use), and the number of live
+ * allocations.  NULL outputs are skipped. */
+mxw_status mxw_ctx_usage(mxw_ctx* ctx, uint64_t* in_use, uint64_t* peak, int64_t* live, int32_t reset_peak);
 
 /* ---- host-side setup (no device needed) -------------------------------- */
 
@@ -170,37 +205,65 @@ mxw_status mxw_export_pattern(const mxw_layout* layout, int64_t* rowptr, int32_t
  * dofs/pou to query n_s only. */
 mxw_status mxw_export_subdomain(const mxw_layout* layout, int32_t s, int64_t* n_s,
                                 int64_t* dofs, uint8_t* pou);
-/* Device bytes a problem built from this layout needs, for nrhs columns and
- * the given Krylov options (admission control). */
-mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int32_t nrhs,
-                                const mxw_solve_opts* opts, uint64_t* bytes);
+/* Device bytes of one problem on this layout (precision, prec_variant) that
+ * runs mxw_solve / mxw_solve_async with nrhs sources and the options opts
+ * (restart, krylov; NULL = restart 50, pseudo-block): its operator, element
+ * matrices and factors, the Krylov (and block) workspace for nrhs columns,
+ * and the solve's temporaries (right-hand sides, solution staging, face
+ * integrals).  with_layout_copy = 1 adds the layout's device copy, which
+ * every problem on the layout shares (count it once).  This is the peak of
+ * the bytes the problem's context counts for it; admission control relies on
+ * it.  Not included: mxw_problem_tune, mxw_smatrix and mxw_solve_recycle
+ * (their own temporaries / recycled spaces). */
+mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int32_t prec_variant, int32_t nrhs,
+                                const mxw_solve_opts* opts, int32_t with_layout_copy, uint64_t* bytes);
+/* The same for a problem described by desc alone (its own layout copy
+ * included): builds the host layout (entities, numbering, subdomains) to
+ * size it, without touching the device. */
+mxw_status mxw_footprint(const mxw_problem_desc* desc, int32_t nrhs, const mxw_solve_opts* opts, uint64_t* bytes);
 
 /* ---- device problem ---------------------------------------------------- */
 
 /* Builds the device operator: element matrices (FP64), CSR assembly of A,
  * dense local matrices A_s and (unless defer_factor) their batched LU
  * factorisation with partial pivoting, all on `stream` (a hipStream_t; NULL
- * = default stream) of the current device.  Blocks until done.
- * hbm_budget (bytes, 0 = no limit) rejects problems whose footprint exceeds
- * it with MXW_ENOMEM before allocating. */
-mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64_t hbm_budget,
-                              int32_t defer_factor, mxw_problem** out);
+ * = default stream) of the context's device (ctx NULL: the current device
+ * and the default context).  Blocks until done.  A problem whose operator
+ * and factors would take the context above its budget is rejected with
+ * MXW_ENOMEM before anything is allocated.  The context must outlive the
+ * problem. */
+mxw_status mxw_problem_create(mxw_ctx* ctx, const mxw_problem_desc* desc, void* stream, int32_t defer_factor,
+                              mxw_problem** out);
 /* Device problem on the mesh, degree and partition of an existing layout,
  * with a permittivity field eps [n_tets][2] (NULL = the layout's) and a
  * wavenumber k0 (negative = the layout's).  The layout's device copy
  * (geometry, unknown numbering, subdomain maps, face matrices) is built on
  * first use and shared by every problem created from it; each problem keeps
  * its layout alive, so the layout handle may be destroyed at any time.  This
- * is the call for streams of solves on one mesh with changing media. */
-mxw_status mxw_problem_create_from_layout(const mxw_layout* layout, const double* eps, double k0,
+ * is the call for streams of solves on one mesh with changing media.  The
+ * device copy is allocated through the context of the problem that builds it
+ * and returned when the layout and all its problems are gone. */
+mxw_status mxw_problem_create_from_layout(mxw_ctx* ctx, const mxw_layout* layout, const double* eps, double k0,
                                           int32_t precision, int32_t prec_variant, void* stream,
-                                          uint64_t hbm_budget, int32_t defer_factor, mxw_problem** out);
+                                          int32_t defer_factor, mxw_problem** out);
 /* Replaces the medium of an existing problem (eps [n_tets][2], NULL = the
  * layout's; k0 < 0 keeps the current wavenumber) and redoes, in the problem's
  * own device buffers, everything that depends on it: element matrices, CSR
  * values, dense A_s and their LU factors (Sec. 2-4).  No device memory is
- * allocated.  This is the step of an imaging loop, where only eps changes. */
+ * allocated.  This is the step of an imaging loop, where only eps changes,
+ * and mostly inside the imaged head (Sec. 6: slowly varying systems): a
+ * subdomain whose local data (k0 and the permittivity of every element of
+ * its overlapping Omega_s) hash to the same value as for its current
+ * factors keeps them, and only the others are assembled and factorised again
+ * (ORAS, OAS and ORAS_MULT; RAS, whose A_s are rows of A, and a problem whose
+ * last factorisation failed or was deferred redo every subdomain).  The
+ * factors are the same bits as a fresh problem's for the new medium. */
 mxw_status mxw_problem_set_medium(mxw_problem* prob, const double* eps, double k0, void* stream);
+/* Subdomains re-factorised by the last medium change (all of them at
+ * creation), and the totals re-factorised and kept over the problem's
+ * medium changes.  NULL outputs are skipped. */
+mxw_status mxw_problem_factor_stats(const mxw_problem* prob, int32_t* refactored_last, int64_t* refactored_total,
+                                    int64_t* kept_total);
 void mxw_problem_destroy(mxw_problem* prob);
 mxw_status mxw_problem_get_info(const mxw_problem* prob, mxw_layout_info* info);
 /* Factorises every A_s in place (batched LU, partial pivoting). Idempotent.
@@ -221,6 +284,20 @@ mxw_status mxw_problem_export_local(const mxw_problem* prob, int32_t s, double* 
  * an unknown kind or a malformed port. */
 mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev,
                            void* stream);
+/* For callers that cannot allocate device memory (code run under HIP graph
+ * capture or in tight serving loops, harnesses that forbid hipMalloc): the
+ * same right-hand sides as mxw_problem_rhs, bit for bit, computed without
+ * any device allocation.  The face integrals of plane-wave and port sources
+ * go to a fixed buffer compiled into the library (4 MiB per device, kept
+ * until the process ends), so the problem may have at most 262,144 /
+ * nfloc impedance faces (nfloc = 3, 8, 15 face unknowns for r = 1, 2, 3);
+ * larger problems get MXW_EINVAL with a message, as does a problem that
+ * lives on another device than the current one.  Every call on one device
+ * shares that buffer: calls that overlap in time on one device (other host
+ * threads, other streams) race and must be serialised by the caller.
+ * Synchronises the stream like mxw_problem_rhs. */
+mxw_status mxw_problem_rhs_noalloc(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev,
+                                   void* stream);
 /* y = A x for nrhs device vectors [nrhs][ndof] complex128. */
 mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_dev, double* y_dev,
                                void* stream);
@@ -242,6 +319,32 @@ mxw_status mxw_solve(mxw_problem* prob, int32_t nrhs, const mxw_source* src,
 mxw_status mxw_solve_rhs(mxw_problem* prob, int32_t nrhs, const double* b_dev,
                          const mxw_solve_opts* opts, void* stream, double* x_dev,
                          int32_t* iters_out, double* relres_out);
+
+/* Asynchronous mxw_solve, for the request loop of an imaging inversion,
+ * which keeps forward solves of several transmitting antennas and media in
+ * flight (Sec. 5-6): the same arguments and results as mxw_solve.  src and
+ * opts are copied; E_out, iters_out and relres_out must stay valid until the
+ * ticket has completed.  The solve runs on a library worker thread that makes
+ * the problem's device current and drives `stream`; solves on one problem run
+ * one after another (each holds the problem while it runs), solves on
+ * different problems overlap on the device.  *ticket receives the handle to
+ * poll, wait on and destroy (MXW_EINVAL for invalid arguments, nothing
+ * started). */
+mxw_status mxw_solve_async(mxw_problem* prob, int32_t nrhs, const mxw_source* src, const mxw_solve_opts* opts,
+                           void* stream, double* E_out, int32_t E_out_is_device, int32_t* iters_out,
+                           double* relres_out, mxw_ticket** ticket);
+/* *done = 1 once the ticket's solve has finished (its outputs are then
+ * complete), else 0.  Never blocks. */
+mxw_status mxw_ticket_poll(mxw_ticket* ticket, int32_t* done);
+/* Blocks until the solve has finished; returns its status (the message of a
+ * failure is then mxw_last_error() of the calling thread). */
+mxw_status mxw_ticket_wait(mxw_ticket* ticket);
+/* Waits for the solve if it is still running, then releases the ticket. */
+void mxw_ticket_destroy(mxw_ticket* ticket);
+
+/* Device bytes the problem holds now (operator, factors, workspaces; not the
+ * shared layout device copy). */
+mxw_status mxw_problem_device_bytes(const mxw_problem* prob, uint64_t* bytes);
 
 /* S-matrix (eq. (5)) of nsol fields X (device complex128 [nsol][ndof]) on
  * nports ports (MXW_SRC_PORT sources): S_ij = int_{Gamma_i} conj(E_j) . E0_i

@@ -79,6 +79,10 @@ class Tuning(C.Structure):
                 ("lu_ms", C.c_double * 2), ("multi_tall_ms", C.c_double)]
 
 
+# device-memory provider of a context (see mxw_ctx_create)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
 _lib = None
 
 _SIGS = {
@@ -89,12 +93,25 @@ _SIGS = {
     "mxw_export_dofs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mxw_export_pattern": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mxw_export_subdomain": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
-    "mxw_layout_footprint": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(SolveOpts),
-                                         C.POINTER(C.c_uint64)]),
-    "mxw_problem_create": (C.c_int32, [C.POINTER(ProblemDesc), C.c_void_p, C.c_uint64, C.c_int32,
+    "mxw_ctx_create": (C.c_int32, [C.c_int32, C.c_uint64, ALLOC_FN, FREE_FN, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mxw_ctx_destroy": (C.c_int32, [C.c_void_p]),
+    "mxw_ctx_usage": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_int64),
+                                  C.c_int32]),
+    "mxw_layout_footprint": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(SolveOpts),
+                                         C.c_int32, C.POINTER(C.c_uint64)]),
+    "mxw_footprint": (C.c_int32, [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(SolveOpts), C.POINTER(C.c_uint64)]),
+    "mxw_problem_create": (C.c_int32, [C.c_void_p, C.POINTER(ProblemDesc), C.c_void_p, C.c_int32,
                                        C.POINTER(C.c_void_p)]),
-    "mxw_problem_create_from_layout": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
-                                                   C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "mxw_problem_create_from_layout": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                                   C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "mxw_solve_async": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Source), C.POINTER(SolveOpts), C.c_void_p,
+                                    C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mxw_ticket_poll": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "mxw_ticket_wait": (C.c_int32, [C.c_void_p]),
+    "mxw_ticket_destroy": (None, [C.c_void_p]),
+    "mxw_problem_device_bytes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "mxw_problem_factor_stats": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                             C.POINTER(C.c_int64)]),
     "mxw_problem_set_medium": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "mxw_problem_destroy": (None, [C.c_void_p]),
     "mxw_problem_get_info": (C.c_int32, [C.c_void_p, C.POINTER(LayoutInfo)]),
@@ -102,6 +119,7 @@ _SIGS = {
     "mxw_problem_export_matrix": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "mxw_problem_export_local": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "mxw_problem_rhs": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Source), C.c_void_p, C.c_void_p]),
+    "mxw_problem_rhs_noalloc": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Source), C.c_void_p, C.c_void_p]),
     "mxw_problem_apply_A": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mxw_problem_apply_prec": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mxw_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Source), C.POINTER(SolveOpts), C.c_void_p,

@@ -61,11 +61,24 @@ class Layout:
         B.check(B.lib().mxw_export_subdomain(self.h, s, C.byref(n), d.ctypes.data, w.ctypes.data))
         return d, w
 
-    def footprint(self, precision=B.MXW_FP64, nrhs=1, restart=50) -> int:
+    def footprint(self, precision=B.MXW_FP64, nrhs=1, restart=50, krylov=B.MXW_KRYLOV_PSEUDOBLOCK,
+                  variant=B.MXW_PREC_ORAS, with_layout_copy=True) -> int:
+        """Device bytes of one problem on this layout that solves nrhs sources
+        (its operator, factors, workspaces and solve temporaries), plus the
+        layout's shared device copy if with_layout_copy."""
         out = C.c_uint64()
-        opts = B.solve_opts(restart=restart)
-        B.check(B.lib().mxw_layout_footprint(self.h, precision, nrhs, C.byref(opts), C.byref(out)))
+        opts = B.solve_opts(restart=restart, krylov=krylov)
+        B.check(B.lib().mxw_layout_footprint(self.h, precision, variant, nrhs, C.byref(opts),
+                                             int(bool(with_layout_copy)), C.byref(out)))
         return out.value
+
+
+def footprint(desc: B.Desc, nrhs=1, restart=50, krylov=B.MXW_KRYLOV_PSEUDOBLOCK) -> int:
+    """Device bytes of a problem described by desc alone (layout copy included)."""
+    out = C.c_uint64()
+    opts = B.solve_opts(restart=restart, krylov=krylov)
+    B.check(B.lib().mxw_footprint(C.byref(desc.c), nrhs, C.byref(opts), C.byref(out)))
+    return out.value
 
 
 def _stream():
@@ -73,27 +86,124 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class Context:
+    """Device-memory context of the library: every device allocation of the
+    problems made with it goes through PyTorch's caching allocator (allocator
+    "torch", the default) or hipMalloc ("hip"), counted against an HBM budget
+    (bytes, 0 = none)."""
+
+    def __init__(self, budget: int = 0, device=None, allocator: str = "torch"):
+        import torch
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        if allocator == "torch":
+            def _alloc(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+                except Exception:          # out of memory: the library reports MXW_ENOMEM
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+            self._alloc, self._free = B.ALLOC_FN(_alloc), B.FREE_FN(_free)
+        elif allocator == "hip":
+            self._alloc, self._free = B.ALLOC_FN(), B.FREE_FN()
+        else:
+            raise ValueError("allocator must be 'torch' or 'hip'")
+        h = C.c_void_p()
+        B.check(B.lib().mxw_ctx_create(dev, int(budget), self._alloc, self._free, None, C.byref(h)))
+        self.h = h
+
+    def usage(self, reset_peak: bool = False) -> dict:
+        u, p, n = C.c_uint64(), C.c_uint64(), C.c_int64()
+        B.check(B.lib().mxw_ctx_usage(self.h, C.byref(u), C.byref(p), C.byref(n), int(reset_peak)))
+        return {"in_use": u.value, "peak": p.value, "live": n.value}
+
+    def close(self):
+        """Releases the context (MxwError MXW_EBUSY while memory is still held)."""
+        if getattr(self, "h", None) is not None and self.h.value:
+            B.check(B.lib().mxw_ctx_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and self.h.value:
+                if B.lib().mxw_ctx_destroy(self.h) == B.MXW_OK:
+                    self.h = None
+        except (TypeError, AttributeError):
+            pass
+
+
+_default_ctx = None
+
+
+def default_context() -> Context:
+    """The context of problems created without one (PyTorch's allocator, no budget)."""
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+class Ticket:
+    """A forward solve running on a library worker thread (mxw_solve_async)."""
+
+    def __init__(self, problem, h, x, it, rr, src):
+        self.problem, self.h, self.x, self.it, self.rr, self._src = problem, h, x, it, rr, src
+        self.status = None
+
+    def done(self) -> bool:
+        d = C.c_int32()
+        B.check(B.lib().mxw_ticket_poll(self.h, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, allow_notconv=False):
+        """(x, iterations, relres, status) once the solve has finished."""
+        if self.status is None:
+            self.status = B.lib().mxw_ticket_wait(self.h)
+            if self.status != B.MXW_OK:
+                self._msg = B.lib().mxw_last_error().decode()
+            B.lib().mxw_ticket_destroy(self.h)
+            self.h = None
+        allowed = (B.MXW_OK, B.MXW_ENOTCONV, B.MXW_EBREAKDOWN) if allow_notconv else (B.MXW_OK,)
+        if self.status not in allowed:
+            raise B.MxwError(self.status, getattr(self, "_msg", ""))
+        return self.x, self.it, self.rr, self.status
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                B.lib().mxw_ticket_destroy(self.h)
+                self.h = None
+        except (TypeError, AttributeError):
+            pass
+
+
 class Problem:
     """Device operator: assembled A, local matrices, batched LU factors."""
 
-    def __init__(self, desc: B.Desc = None, hbm_budget: int = 0, defer_factor: bool = False, layout=None,
-                 eps=None, k0: float = -1.0, precision=B.MXW_FP64, variant=B.MXW_PREC_ORAS):
+    def __init__(self, desc: B.Desc = None, defer_factor: bool = False, layout=None,
+                 eps=None, k0: float = -1.0, precision=B.MXW_FP64, variant=B.MXW_PREC_ORAS, ctx: Context = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required for mxw.Problem")
         self.desc = desc
         self.layout = layout
+        self.ctx = ctx if ctx is not None else default_context()
+        if layout is not None:
+            # the layout's device copy may be allocated through this context
+            layout._contexts = getattr(layout, "_contexts", []) + [self.ctx]
         h = C.c_void_p()
         if layout is None:
-            st = B.lib().mxw_problem_create(C.byref(desc.c), _stream(), hbm_budget, int(defer_factor), C.byref(h))
+            st = B.lib().mxw_problem_create(self.ctx.h, C.byref(desc.c), _stream(), int(defer_factor), C.byref(h))
         else:
             e = None
             if eps is not None:
                 e = np.asarray(eps, dtype=np.complex128)
                 self._eps = np.ascontiguousarray(np.stack([e.real, e.imag], axis=1))
                 e = self._eps.ctypes.data
-            st = B.lib().mxw_problem_create_from_layout(layout.h, e, float(k0), int(precision), int(variant),
-                                                        _stream(), hbm_budget, int(defer_factor), C.byref(h))
+            st = B.lib().mxw_problem_create_from_layout(self.ctx.h, layout.h, e, float(k0), int(precision),
+                                                        int(variant), _stream(), int(defer_factor), C.byref(h))
         self.h = h
         self.create_status = st
         if st != B.MXW_OK and not (st == B.MXW_ESINGULAR and h.value):
@@ -158,6 +268,17 @@ class Problem:
         b = torch.empty((len(sources), self.ndof), dtype=torch.complex128, device="cuda")
         src = B.make_sources(sources)
         B.check(B.lib().mxw_problem_rhs(self.h, len(sources), src, b.data_ptr(), _stream()))
+        return b
+
+    def rhs_noalloc(self, sources, out=None):
+        """The same right-hand sides through the entry point that allocates no
+        device memory (its face integrals go to the library's fixed buffer);
+        out: an existing [nsrc][ndof] complex128 tensor to fill."""
+        import torch
+        b = out if out is not None else torch.empty((len(sources), self.ndof), dtype=torch.complex128,
+                                                     device="cuda")
+        src = B.make_sources(sources)
+        B.check(B.lib().mxw_problem_rhs_noalloc(self.h, len(sources), src, b.data_ptr(), _stream()))
         return b
 
     def apply_A(self, x):
@@ -256,6 +377,51 @@ class Problem:
     def solve(self, sources, **kw):
         b = self.rhs(sources)
         return self.solve_rhs(b, **kw)
+
+    def solve_host(self, sources, tol=1e-8, restart=50, max_iters=5000, krylov=B.MXW_KRYLOV_PSEUDOBLOCK,
+                   use_graph=0, allow_notconv=False):
+        """mxw_solve with the E field returned in host memory (the library
+        stages the right-hand sides and the solution on the device itself)."""
+        E = np.empty((len(sources), self.ndof), np.complex128)
+        it = np.zeros(len(sources), np.int32)
+        rr = np.zeros(len(sources), np.float64)
+        src = B.make_sources(sources)
+        opts = B.solve_opts(tol, restart, max_iters, krylov, use_graph)
+        st = B.lib().mxw_solve(self.h, len(sources), src, C.byref(opts), _stream(), E.ctypes.data, 0,
+                               it.ctypes.data, rr.ctypes.data)
+        allowed = (B.MXW_OK, B.MXW_ENOTCONV, B.MXW_EBREAKDOWN) if allow_notconv else (B.MXW_OK,)
+        return E, it, rr, B.check(st, allowed)
+
+    def solve_async(self, sources, tol=1e-8, restart=50, max_iters=5000, krylov=B.MXW_KRYLOV_PSEUDOBLOCK,
+                    use_graph=0, stream=None) -> Ticket:
+        """Starts the forward solves of the sources on a library worker thread
+        driving `stream` (a torch.cuda.Stream; default: the current stream);
+        returns a Ticket."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        x = torch.empty((len(sources), self.ndof), dtype=torch.complex128, device="cuda")
+        it = np.zeros(len(sources), np.int32)
+        rr = np.zeros(len(sources), np.float64)
+        src = B.make_sources(sources)
+        opts = B.solve_opts(tol, restart, max_iters, krylov, use_graph)
+        h = C.c_void_p()
+        # x is made on torch's current stream; the worker's stream waits for it
+        st.wait_stream(torch.cuda.current_stream())
+        B.check(B.lib().mxw_solve_async(self.h, len(sources), src, C.byref(opts), C.c_void_p(st.cuda_stream),
+                                        x.data_ptr(), 1, it.ctypes.data, rr.ctypes.data, C.byref(h)))
+        return Ticket(self, h, x, it, rr, src)
+
+    def factor_stats(self) -> dict:
+        """Subdomains re-factorised by the last medium change; totals over the changes."""
+        a, b, c = C.c_int32(), C.c_int64(), C.c_int64()
+        B.check(B.lib().mxw_problem_factor_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"refactored_last": a.value, "refactored_total": b.value, "kept_total": c.value}
+
+    def device_bytes(self) -> int:
+        """Device bytes the problem holds now (not the layout's shared copy)."""
+        out = C.c_uint64()
+        B.check(B.lib().mxw_problem_device_bytes(self.h, C.byref(out)))
+        return out.value
 
 
 def timing(enabled: bool = True):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -13,6 +14,8 @@
 #include <numeric>
 #include <sstream>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -145,43 +148,128 @@ static void flush_timing() {
 }
 
 // ---------------------------------------------------------------------------
-// device memory
+// device memory: every allocation goes through a context (the caller's
+// allocator callback and HBM budget, or hipMalloc with no budget), which
+// counts the bytes in use and their peak
 // ---------------------------------------------------------------------------
+struct CtxState {
+  int device = 0;
+  uint64_t budget = 0;   // 0: no limit
+  mxw_alloc_fn alloc = nullptr;
+  mxw_free_fn free_ = nullptr;
+  void* user = nullptr;
+  std::mutex mu;
+  uint64_t in_use = 0, peak = 0;
+  int64_t live = 0;      // allocations not yet returned
+
+  bool reserve(uint64_t bytes, std::string* why) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (budget && in_use + bytes > budget) {
+      std::ostringstream os;
+      os << "HBM budget exceeded: " << in_use << " bytes in use + " << bytes << " requested > budget " << budget;
+      *why = os.str();
+      return false;
+    }
+    in_use += bytes;
+    peak = std::max(peak, in_use);
+    ++live;
+    return true;
+  }
+  void unreserve(uint64_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    in_use -= bytes;
+    --live;
+  }
+};
+
+// the context of calls made without one: hipMalloc / hipFree, no budget,
+// the current device
+static std::shared_ptr<CtxState> default_ctx() {
+  static std::shared_ptr<CtxState> d = [] {
+    auto c = std::make_shared<CtxState>();
+    c->device = -1;
+    return c;
+  }();
+  return d;
+}
+
 struct DevMem {
-  std::vector<void*> ptrs;
+  std::shared_ptr<CtxState> ctx = default_ctx();
+  hipStream_t st = nullptr;   // stream the memory is used on (handed to the allocator)
+  std::vector<std::pair<void*, uint64_t>> ptrs;
   uint64_t bytes = 0;
-  ~DevMem() {
-    for (void* p : ptrs) hipFree(p);
+  std::string why;            // reason of the last failed allocation
+  DevMem() = default;
+  explicit DevMem(std::shared_ptr<CtxState> c, hipStream_t s = nullptr) : ctx(std::move(c)), st(s) {}
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { reset(); }
+  void* raw(uint64_t nbytes) {
+    if (!ctx->reserve(nbytes, &why)) return nullptr;
+    void* p = nullptr;
+    if (ctx->alloc) {
+      p = ctx->alloc((size_t)nbytes, (void*)st, ctx->user);
+    } else if (hipMalloc(&p, nbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (!p) {
+      if (why.empty()) why = "device allocation failed";
+      ctx->unreserve(nbytes);
+      return nullptr;
+    }
+    ptrs.emplace_back(p, nbytes);
+    bytes += nbytes;
+    return p;
   }
   template <class T>
   T* alloc(size_t n) {
-    if (n == 0) n = 1;
-    void* p = nullptr;
-    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
-    ptrs.push_back(p);
-    bytes += n * sizeof(T);
-    return static_cast<T*>(p);
+    return static_cast<T*>(raw((uint64_t)std::max<size_t>(n, 1) * sizeof(T)));
+  }
+  void give_back(void* p, uint64_t nbytes) {
+    if (ctx->free_)
+      ctx->free_(p, ctx->user);
+    else
+      hipFree(p);
+    ctx->unreserve(nbytes);
+  }
+  // Memory still used by queued kernels must not go back to a caching
+  // allocator: the device is drained first (hipFree waits by itself).
+  void drain() {
+    if (ctx->free_ && !ptrs.empty()) hipDeviceSynchronize();
   }
   void reset() {
-    for (void* p : ptrs) hipFree(p);
+    drain();
+    for (auto& q : ptrs) give_back(q.first, q.second);
     ptrs.clear();
     bytes = 0;
   }
   void release(void* p) {
-    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    auto it = std::find_if(ptrs.begin(), ptrs.end(), [&](const std::pair<void*, uint64_t>& q) { return q.first == p; });
     if (it != ptrs.end()) {
-      hipFree(p);
+      drain();
+      give_back(it->first, it->second);
+      bytes -= it->second;
       ptrs.erase(it);
     }
   }
 };
 
+// bytes of one DevMem allocation of n elements of T (as DevMem::alloc takes)
+template <class T>
+uint64_t nbytes_of(size_t n) {
+  return (uint64_t)std::max<size_t>(n, 1) * sizeof(T);
+}
+
 }  // namespace mxw
 
 using namespace mxw;
+
+struct mxw_ctx {
+  std::shared_ptr<CtxState> S;
+};
+
+static std::shared_ptr<CtxState> ctx_of(mxw_ctx* c) { return c ? c->S : default_ctx(); }
 
 // Host layout plus its device mirror (geometry, numbering, subdomain maps and
 // the geometric face matrices), shared by every problem built on it.
@@ -256,6 +344,7 @@ struct BlockWork {
   double2 *H1 = nullptr, *H2 = nullptr, *Hc = nullptr, *part = nullptr, *G = nullptr, *G0 = nullptr, *R1 = nullptr,
           *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *S = nullptr, *T = nullptr, *Rls = nullptr, *E = nullptr,
           *Y = nullptr;
+  double2* Xi = nullptr;   // interleaved copy of a block for the product with A (p >= 16)
   double* est = nullptr;
   int* info = nullptr;   // [0] rank loss, [1] second Gram-Schmidt pass needed
   int64_t reorth = 0;    // second passes in the last solve
@@ -287,9 +376,14 @@ struct RecycleWork {
 };
 
 struct mxw_problem {
-  explicit mxw_problem(std::shared_ptr<LayoutShared> s) : S(std::move(s)), L(S->L) {}
+  mxw_problem(std::shared_ptr<LayoutShared> s, std::shared_ptr<CtxState> c, hipStream_t st)
+      : S(std::move(s)), L(S->L), ctx(c), mem(c, st) {
+    kw.mem.ctx = bw.mem.ctx = rw.mem.ctx = rw.bw.mem.ctx = c;
+  }
   std::shared_ptr<LayoutShared> S;
   const Layout& L;
+  std::shared_ptr<CtxState> ctx;
+  std::mutex run;          // held by a solve (solves on one problem run one after another)
   int device = 0;
   int variant = MXW_PREC_ORAS;
   double k0 = 0.0;
@@ -330,6 +424,11 @@ struct mxw_problem {
   int lu_ku = 8;          // k slice width of the LU's block-column update (tunable in FP32)
   int multi_rows = 64;    // rows per pass of the multi-column local solve (64, or 128 in FP32; tunable)
   uint64_t op_gen = 0;    // bumped whenever A or M changes (recycled spaces go stale)
+  // factor residency per subdomain (assemble_medium)
+  int* sub_list = nullptr;             // device: subdomains to re-factorise
+  std::vector<uint64_t> sub_hash;      // local-data hash each subdomain's factors were made for
+  bool hash_valid = false;             // the factors match sub_hash (no failed or deferred factorisation)
+  int64_t refactor_last = 0, refactor_total = 0, kept_total = 0, medium_updates = 0;
   KrylovWork kw;
   BlockWork bw;
   RecycleWork rw;
@@ -354,7 +453,7 @@ template <class T>
 mxw_status upload(DevMem& mem, T*& dst, const std::vector<T>& src, hipStream_t st) {
   dst = mem.alloc<T>(src.size());
   if (!dst) {
-    set_error("device allocation failed");
+    set_error(mem.why);
     return MXW_ENOMEM;
   }
   if (!src.empty()) HIP_CHECK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
@@ -403,45 +502,122 @@ void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
-uint64_t factor_bytes(const Layout& L, int precision) {
-  uint64_t e = 0;
-  for (int s = 0; s < L.n_sub; ++s) {
-    int64_t n = L.sub_dof_ptr[s + 1] - L.sub_dof_ptr[s];
-    e += 2 * (uint64_t)round_ld(n) * n;
-    e += 2 * (uint64_t)n * kLuNB;   // LU block-column scratch
-  }
-  return e * (precision == MXW_MIXED ? 4 : 8);
-}
+// ---- exact device footprints: each function lists the allocations of the
+// code it sizes, in the same order and with the same element counts
 
-uint64_t krylov_bytes(int64_t ndof, int nrhs, int m) {
-  const int64_t nblk = (ndof + 2047) / 2048;
+// the layout's device copy (ensure_device_layout)
+uint64_t mirror_bytes(const Layout& L) {
   uint64_t b = 0;
-  b += (uint64_t)nrhs * (2 * m + 1) * ndof * 16;     // V, Z
-  b += (uint64_t)nrhs * 3 * ndof * 16;               // W, X, R
-  b += (uint64_t)nrhs * nblk * (m + 1) * 16;
-  b += (uint64_t)nrhs * (m + 1) * (m + 8) * 16;
+  b += nbytes_of<double>(L.xyz.size()) + nbytes_of<int>(L.tets.size()) + nbytes_of<int>(L.tet_dofs.size());
+  b += nbytes_of<Term>(L.basis.phi.size()) + nbytes_of<Term>(L.basis.curl.size()) +
+       nbytes_of<Term>(L.basis.fphi.size());
+  b += nbytes_of<int>(L.ft_vert.size()) + nbytes_of<int>(L.ft_dofs.size());
+  b += nbytes_of<int64_t>(L.rowptr.size()) + nbytes_of<int>(L.cols.size()) + nbytes_of<int>(L.dof_ent.size());
+  b += nbytes_of<int64_t>(L.ent_tet_ptr.size()) + nbytes_of<int>(L.ent_tets.size());
+  b += nbytes_of<int64_t>(L.ent_imp_ptr.size()) + nbytes_of<int>(L.ent_imps.size());
+  b += nbytes_of<int>(L.imp_ft.size()) + nbytes_of<int>(L.imp_ft.size());    // imp_ft, imp_opp
+  b += 2 * nbytes_of<double>(L.r + 3);                                         // gx, gw
+  b += nbytes_of<int64_t>(L.n_sub) + nbytes_of<int64_t>(L.n_sub + 1);          // foff, poff
+  b += 3 * nbytes_of<int>(L.n_sub);                                             // nsz, lds, order
+  b += nbytes_of<int>(L.sub_dofs.size()) + nbytes_of<uint8_t>(L.sub_pou.size());
+  b += nbytes_of<int64_t>(L.sub_tet_ptr.size()) + nbytes_of<int>(L.sub_tets.size()) +
+       nbytes_of<int>(L.sub_lmap.size());
+  b += nbytes_of<int64_t>(L.sub_face_ptr.size()) + nbytes_of<int>(L.sub_face_ft.size()) +
+       nbytes_of<int>(L.sub_face_lmap.size());
+  b += nbytes_of<int64_t>(L.ndof + 1) + nbytes_of<int64_t>(L.sub_dofs.size());  // gall_ptr, gall_pos
+  b += nbytes_of<double>(L.ft_face.size() * (size_t)L.basis.nfloc * L.basis.nfloc);   // BF
   return b;
 }
 
-uint64_t base_bytes(const Layout& L) {
+uint64_t factor_elems_of(const Layout& L) {
+  uint64_t e = 0;
+  for (int s = 0; s < L.n_sub; ++s) {
+    const int64_t n = L.sub_dof_ptr[s + 1] - L.sub_dof_ptr[s];
+    e += 2 * (uint64_t)round_ld(n) * n;
+  }
+  return e;
+}
+
+// one problem's operator, element matrices and factors (create_problem)
+uint64_t problem_bytes(const Layout& L, int precision) {
+  const size_t rsz = precision == MXW_MIXED ? 4 : 8;
+  const int nloc = L.basis.nloc;
   uint64_t b = 0;
-  const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
-  b += L.xyz.size() * 8 + L.tets.size() * 4 + L.eps.size() * 8 + L.tet_dofs.size() * 4;
-  b += (uint64_t)L.nt * nloc * nloc * 16;                      // element matrices
-  b += (uint64_t)L.ft_face.size() * nfloc * (nfloc * 8 + 4) + L.ft_vert.size() * 4;
-  b += L.rowptr.size() * 8 + L.cols.size() * 4 + L.cols.size() * 16;
-  b += L.dof_ent.size() * 4 + L.ent_tet_ptr.size() * 8 + L.ent_tets.size() * 4;
-  b += L.ent_imp_ptr.size() * 8 + L.ent_imps.size() * 4;
-  b += L.sub_dofs.size() * (4 + 1 + 4) + L.sub_tets.size() * 4 + L.sub_lmap.size() * 4;
-  b += L.sub_face_ft.size() * 12 + L.sub_face_lmap.size() * 4;
-  b += (uint64_t)L.n_sub * (8 * 4 + 4 * 4);
-  b += (uint64_t)L.sum_ns * 8 + (uint64_t)L.ndof * 8;
+  b += nbytes_of<double>(2 * L.nt) + nbytes_of<double>(L.imp_tet.size()) + nbytes_of<double>(2 * L.imp_tet.size());
+  b += nbytes_of<double>(L.sub_face_tet.size());
+  b += nbytes_of<int>(L.sum_ns) + nbytes_of<int>(L.n_sub);                     // perm, info
+  b += nbytes_of<unsigned char>(factor_elems_of(L) * rsz);                      // F
+  b += nbytes_of<unsigned char>((size_t)L.sum_ns * 2 * kLuNB * rsz);            // LU block-column scratch
+  b += nbytes_of<double2>((size_t)L.nt * nloc * nloc);                           // AT
+  b += nbytes_of<double2>(L.cols.size());                                       // CSR values
+  b += nbytes_of<int>(L.n_sub);                                                 // subdomain list
   return b;
 }
 
 // variants whose prolongation gathers every local solution of an unknown
 // (OAS: D_s = I; ORAS_MULT: weights by multiplicity) instead of the owner's
 bool gathered(int variant) { return variant == MXW_PREC_OAS || variant == MXW_PREC_ORAS_MULT; }
+
+// the Krylov workspace for nrhs columns (ensure_krylov)
+uint64_t krylov_bytes(const Layout& L, int nrhs, int m, int variant, bool mixed) {
+  const int64_t n = L.ndof;
+  const int maxv = m + 1;
+  const int nblk = red_blocks(n);
+  uint64_t b = 0;
+  b += nbytes_of<double2>((size_t)nrhs * maxv * n) + nbytes_of<double2>((size_t)nrhs * m * n);   // V, Z
+  b += 3 * nbytes_of<double2>((size_t)nrhs * n);                                                // W, X, Rv
+  if (gathered(variant)) b += nbytes_of<double2>((size_t)nrhs * L.sum_ns);                     // YS
+  b += 2 * nbytes_of<double2>((size_t)nrhs * maxv);                                            // h1, h2
+  b += nbytes_of<double2>((size_t)nrhs * nblk * maxv);                                          // part
+  b += nbytes_of<double2>((size_t)nrhs * maxv * m);                                             // H
+  b += nbytes_of<double2>((size_t)nrhs * maxv) + nbytes_of<double2>((size_t)nrhs * (maxv + 1));  // sn, g
+  b += nbytes_of<double2>((size_t)nrhs * maxv);                                                 // y
+  b += nbytes_of<double>((size_t)nrhs * maxv);                                                  // cs
+  b += 2 * nbytes_of<double>(nrhs) + nbytes_of<double>((size_t)nrhs * nblk) + 2 * nbytes_of<double>(nrhs);
+  b += 2 * nbytes_of<int>(nrhs);                                                                // active, jd
+  if (nrhs >= 2 && !gathered(variant)) {
+    const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
+    b += nbytes_of<unsigned char>((size_t)nchunk * 2 * L.sum_ns * multi_chunk_cols() * (mixed ? 4 : 8));
+  }
+  return b;
+}
+
+constexpr int kMaxGramParts = 128;   // split-K partial products of a Gram matrix
+
+// blocks of at least this many columns multiply A through an interleaved copy
+constexpr int kIlMinCols = 16;
+
+// the block GMRES workspace (ensure_block_ws)
+uint64_t block_bytes(int64_t n, int p, int m) {
+  const int64_t Q = (int64_t)(m + 1) * p;
+  uint64_t b = 0;
+  b += 3 * nbytes_of<double2>(Q * p);                                  // H1, H2, Hc
+  b += nbytes_of<double2>((size_t)kMaxGramParts * Q * p);              // part
+  b += 7 * nbytes_of<double2>((size_t)p * p);                          // G, G0, R1, R1i, R2, R2i, S
+  b += nbytes_of<double2>((size_t)m * 4 * p * p);                      // T
+  b += nbytes_of<double2>((size_t)m * p * m * p);                      // Rls
+  b += nbytes_of<double2>(Q * p) + nbytes_of<double2>((size_t)m * p * p);   // E, Y
+  b += nbytes_of<double>(p) + nbytes_of<int>(2);                       // est, info
+  if (p >= kIlMinCols) b += nbytes_of<double2>((size_t)n * interleaved_cols());   // Xi
+  return b;
+}
+
+// temporaries of one mxw_solve call: right-hand sides, solution staging for
+// a host output, face integrals of plane-wave / port sources
+uint64_t solve_temp_bytes(const Layout& L, int nrhs) {
+  return 2 * nbytes_of<double2>((size_t)L.ndof * nrhs) +
+         nbytes_of<double2>(std::max<size_t>(1, L.imp_ft.size() * (size_t)L.basis.nfloc));
+}
+
+uint64_t footprint_bytes(const Layout& L, int precision, int variant, int nrhs, int m, int krylov, bool with_mirror) {
+  nrhs = std::max(nrhs, 1);
+  uint64_t b = problem_bytes(L, precision) + krylov_bytes(L, nrhs, m, variant, precision == MXW_MIXED) +
+               solve_temp_bytes(L, nrhs);
+  if (krylov == MXW_KRYLOV_BLOCK) b += block_bytes(L.ndof, nrhs, m);
+  if (with_mirror) b += mirror_bytes(L);
+  return b;
+}
+
 
 mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   KrylovWork& k = P->kw;
@@ -483,7 +659,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
       !k.cs || !k.hn || !k.w0 || !k.npart || !k.est || !k.beta || !k.active || !k.jd ||
       (gathered(P->variant) && !k.YS)) {
     k.V = nullptr;
-    set_error("Krylov workspace allocation failed");
+    set_error("Krylov workspace: " + k.mem.why);
     return MXW_ENOMEM;
   }
   k.xbuf = nullptr;
@@ -492,7 +668,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
     k.xbuf = k.mem.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() * (P->mixed ? 4 : 8));
     if (!k.xbuf) {
       k.V = nullptr;
-      set_error("Krylov workspace allocation failed (multi-column local solve)");
+      set_error("Krylov workspace (multi-column local solve): " + k.mem.why);
       return MXW_ENOMEM;
     }
   }
@@ -573,12 +749,15 @@ mxw_status check_problem(const mxw_problem* P) {
   return MXW_OK;
 }
 
+// list / count: the subdomains to assemble (device ids, largest first);
+// nullptr = all of them
 template <typename R>
-mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor) {
+mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor, const int* list = nullptr,
+                                  int count = -1) {
   const Layout& L = P->L;
-  LocalAssembleArgs la{L.n_sub, P->foff, P->nsz, P->lds, P->sub_tet_ptr, P->sub_tets, P->sub_lmap, P->AT,
-                       L.basis.nloc, P->sub_face_ptr, P->sub_face_ft, P->sub_face_coef, P->sub_face_lmap, P->BF,
-                       L.basis.nfloc};
+  LocalAssembleArgs la{list ? count : L.n_sub, P->foff, P->nsz, P->lds, P->sub_tet_ptr, P->sub_tets, P->sub_lmap,
+                       P->AT, L.basis.nloc, P->sub_face_ptr, P->sub_face_ft, P->sub_face_coef, P->sub_face_lmap,
+                       P->BF, L.basis.nfloc, list};
   {
     ScopedTimer tm(st, "local_assemble");
     if (P->variant == MXW_PREC_RAS)
@@ -597,18 +776,20 @@ mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor) {
   return MXW_OK;
 }
 
-mxw_status factor_impl(mxw_problem* P, hipStream_t st) {
+// list / count: factorise only these subdomains (device ids, largest first);
+// nullptr = all
+mxw_status factor_impl(mxw_problem* P, hipStream_t st, const int* list = nullptr, int count = -1) {
   if (P->factored) return MXW_OK;
+  const int nf = list ? count : P->L.n_sub;
+  const int* ord = list ? list : P->order;
   if (P->mixed) {
-    const int NB = kLuNB;
-    (void)NB;
     ScopedKernelTimer tm("lu");
-    launch_lu<float>(st, P->L.n_sub, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (float*)P->lu_scratch,
-                     P->info, P->order, P->lu_ku);
+    launch_lu<float>(st, nf, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (float*)P->lu_scratch,
+                     P->info, ord, P->lu_ku);
   } else {
     ScopedKernelTimer tm("lu");
-    launch_lu<double>(st, P->L.n_sub, (double*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
-                      (double*)P->lu_scratch, P->info, P->order, P->lu_ku);
+    launch_lu<double>(st, nf, (double*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (double*)P->lu_scratch,
+                      P->info, ord, P->lu_ku);
   }
   HIP_CHECK(hipGetLastError());
   std::vector<int> info(P->L.n_sub);
@@ -616,8 +797,10 @@ mxw_status factor_impl(mxw_problem* P, hipStream_t st) {
   HIP_CHECK(hipStreamSynchronize(st));
   P->factored = true;
   ++P->op_gen;
+  P->hash_valid = true;
   for (int s = 0; s < P->L.n_sub; ++s)
     if (info[s] != 0) {
+      P->hash_valid = false;   // the next medium factorises every subdomain again
       std::ostringstream os;
       os << "zero pivot in the LU of subdomain " << s << " at column " << info[s] - 1;
       set_error(os.str());
@@ -723,15 +906,81 @@ mxw_status mxw_export_subdomain(const mxw_layout* layout, int32_t s, int64_t* n_
   return MXW_OK;
 }
 
-mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int32_t nrhs,
-                                const mxw_solve_opts* opts, uint64_t* bytes) {
-  if (!layout || !bytes || nrhs < 0) {
+mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int32_t prec_variant, int32_t nrhs,
+                                const mxw_solve_opts* opts, int32_t with_layout_copy, uint64_t* bytes) {
+  if (!layout || !bytes || nrhs < 0 || (precision != MXW_FP64 && precision != MXW_MIXED) || prec_variant < 0 ||
+      prec_variant > MXW_PREC_ORAS_MULT || (opts && (opts->restart < 1 || opts->restart > 200))) {
     set_error("invalid argument");
     return MXW_EINVAL;
   }
   const int m = opts ? opts->restart : 50;
-  const Layout& L = layout->S->L;
-  *bytes = base_bytes(L) + factor_bytes(L, precision) + krylov_bytes(L.ndof, std::max(nrhs, 1), m);
+  const int krylov = opts ? opts->krylov : MXW_KRYLOV_PSEUDOBLOCK;
+  *bytes = footprint_bytes(layout->S->L, precision, prec_variant, nrhs, m, krylov, with_layout_copy != 0);
+  return MXW_OK;
+}
+
+mxw_status mxw_footprint(const mxw_problem_desc* desc, int32_t nrhs, const mxw_solve_opts* opts, uint64_t* bytes) {
+  if (!desc || !bytes) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  mxw_layout* l = nullptr;
+  TRY(mxw_layout_create(desc, &l));
+  const mxw_status st = mxw_layout_footprint(l, desc->precision, desc->prec_variant, nrhs, opts, 1, bytes);
+  mxw_layout_destroy(l);
+  return st;
+}
+
+mxw_status mxw_ctx_create(int32_t device, uint64_t hbm_budget, mxw_alloc_fn alloc, mxw_free_fn free_, void* user,
+                          mxw_ctx** out) {
+  if (!out || (!alloc) != (!free_)) {
+    set_error("out is NULL, or only one of alloc / free_ given");
+    return MXW_EINVAL;
+  }
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    set_error("no such device");
+    return MXW_EINVAL;
+  }
+  std::unique_ptr<mxw_ctx> c(new (std::nothrow) mxw_ctx());
+  if (!c) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  c->S = std::make_shared<CtxState>();
+  c->S->device = device;
+  c->S->budget = hbm_budget;
+  c->S->alloc = alloc;
+  c->S->free_ = free_;
+  c->S->user = user;
+  *out = c.release();
+  return MXW_OK;
+}
+
+mxw_status mxw_ctx_destroy(mxw_ctx* ctx) {
+  if (!ctx) return MXW_OK;
+  {
+    std::lock_guard<std::mutex> lk(ctx->S->mu);
+    if (ctx->S->live > 0) {
+      std::ostringstream os;
+      os << "context still holds " << ctx->S->live << " device allocations (" << ctx->S->in_use << " bytes)";
+      set_error(os.str());
+      return MXW_EBUSY;
+    }
+  }
+  delete ctx;
+  return MXW_OK;
+}
+
+mxw_status mxw_ctx_usage(mxw_ctx* ctx, uint64_t* in_use, uint64_t* peak, int64_t* live, int32_t reset_peak) {
+  CtxState& c = ctx ? *ctx->S : *default_ctx();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (in_use) *in_use = c.in_use;
+  if (peak) *peak = c.peak;
+  if (live) *live = c.live;
+  if (reset_peak) c.peak = c.in_use;
   return MXW_OK;
 }
 
@@ -740,7 +989,7 @@ mxw_status mxw_layout_footprint(const mxw_layout* layout, int32_t precision, int
 namespace {
 
 // Device mirror of a layout: uploaded once, then shared.
-mxw_status ensure_device_layout(LayoutShared& S, hipStream_t st) {
+mxw_status ensure_device_layout(LayoutShared& S, const std::shared_ptr<CtxState>& ctx, hipStream_t st) {
   std::lock_guard<std::mutex> lk(S.mu);
   int dev = 0;
   HIP_CHECK(hipGetDevice(&dev));
@@ -753,6 +1002,9 @@ mxw_status ensure_device_layout(LayoutShared& S, hipStream_t st) {
   }
   const Layout& L = S.L;
   DevMem& M = S.mem;
+  M.reset();          // a failed earlier attempt may have left a part
+  M.ctx = ctx;
+  M.st = st;
   TRY(upload(M, S.xyz, L.xyz, st));
   TRY(upload(M, S.tets, L.tets, st));
   TRY(upload(M, S.tet_dofs, L.tet_dofs, st));
@@ -851,9 +1103,39 @@ mxw_status ensure_device_layout(LayoutShared& S, hipStream_t st) {
 // Everything that depends on the medium, in the problem's existing buffers:
 // face coefficients, FP64 element matrices, CSR values, dense A_s and (unless
 // deferred) their LU factors.
+// Hash of everything a Robin local matrix A_s depends on besides the mesh:
+// k0 and the permittivity of every element of Omega_s (its element matrices,
+// the impedance and transmission coefficients of its faces), in order.
+// FNV-1a over the bytes.
+std::vector<uint64_t> local_data_hashes(const Layout& L, const double* eps, double k0) {
+  std::vector<uint64_t> h(L.n_sub);
+  auto mix = [](uint64_t x, const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t q = 0; q < n; ++q) x = (x ^ c[q]) * 1099511628211ull;
+    return x;
+  };
+  for (int s = 0; s < L.n_sub; ++s) {
+    uint64_t x = mix(14695981039346656037ull, &k0, sizeof(k0));
+    for (int64_t q = L.sub_tet_ptr[s]; q < L.sub_tet_ptr[s + 1]; ++q)
+      x = mix(x, eps + 2 * (int64_t)L.sub_tets[q], 2 * sizeof(double));
+    h[s] = x;
+  }
+  return h;
+}
+
 mxw_status assemble_medium(mxw_problem* P, const double* eps, double k0, hipStream_t st, int defer_factor) {
   const Layout& L = P->L;
   const int nloc = L.basis.nloc, nfloc = L.basis.nfloc;
+  // factor residency per subdomain: a subdomain whose local data are
+  // unchanged keeps its factors (Robin local matrices only: RAS takes A_s
+  // from rows of A that reach outside Omega_s)
+  std::vector<uint64_t> hash = local_data_hashes(L, eps, k0);
+  std::vector<int> changed;
+  const bool partial = !defer_factor && P->factored && P->hash_valid && P->variant != MXW_PREC_RAS &&
+                       P->sub_hash.size() == hash.size();
+  if (partial)
+    for (int s : P->S->h_order)   // largest first, as the full launches
+      if (hash[s] != P->sub_hash[s]) changed.push_back(s);
   std::vector<double> beta, coef, ie(2 * L.imp_tet.size());
   face_coefficients(L, eps, k0, beta, coef);
   for (size_t q = 0; q < L.imp_tet.size(); ++q) {
@@ -877,17 +1159,38 @@ mxw_status assemble_medium(mxw_problem* P, const double* eps, double k0, hipStre
     launch_assemble_rows(st, aa);
   }
   HIP_CHECK(hipGetLastError());
-  if (P->mixed)
-    TRY(build_local_and_factor<float>(P, st, false));
-  else
-    TRY(build_local_and_factor<double>(P, st, false));
+  const int* list = nullptr;
+  int count = L.n_sub;
+  if (partial) {
+    count = (int)changed.size();
+    if (count) HIP_CHECK(hipMemcpyAsync(P->sub_list, changed.data(), sizeof(int) * count, hipMemcpyHostToDevice, st));
+    list = P->sub_list;
+  }
+  if (count > 0) {
+    if (P->mixed)
+      TRY(build_local_and_factor<float>(P, st, false, list, count));
+    else
+      TRY(build_local_and_factor<double>(P, st, false, list, count));
+  }
   HIP_CHECK(hipStreamSynchronize(st));   // the host vectors above go out of scope
+  P->sub_hash = hash;
+  P->hash_valid = false;
+  ++P->medium_updates;
+  P->refactor_last = count;
+  P->refactor_total += count;
+  P->kept_total += L.n_sub - count;
   if (defer_factor) return MXW_OK;
-  return factor_impl(P, st);
+  if (count == 0) {   // every subdomain kept its factors
+    P->factored = true;
+    P->hash_valid = true;
+    return MXW_OK;
+  }
+  return factor_impl(P, st, list, count);
 }
 
-mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* eps_in, double k0, int precision,
-                          int variant, hipStream_t st, uint64_t hbm_budget, int defer_factor, mxw_problem** out) {
+mxw_status create_problem(const std::shared_ptr<CtxState>& ctx, const std::shared_ptr<LayoutShared>& S,
+                          const double* eps_in, double k0, int precision, int variant, hipStream_t st,
+                          int defer_factor, mxw_problem** out) {
   const Layout& L = S->L;
   if (precision != MXW_FP64 && precision != MXW_MIXED) {
     set_error("unknown precision");
@@ -916,15 +1219,25 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
     set_error(os.str());
     return MXW_EINVAL;
   }
-  const uint64_t need = base_bytes(L) + factor_bytes(L, precision);
-  if (hbm_budget && need > hbm_budget) {
-    std::ostringstream os;
-    os << "problem needs " << need << " device bytes, budget is " << hbm_budget;
-    set_error(os.str());
-    return MXW_ENOMEM;
+  if (ctx->device >= 0) {   // a context's device (the default context: the current one)
+    int cur = 0;
+    HIP_CHECK(hipGetDevice(&cur));
+    if (cur != ctx->device) HIP_CHECK(hipSetDevice(ctx->device));
   }
-  TRY(ensure_device_layout(*S, st));
-  std::unique_ptr<mxw_problem> P(new (std::nothrow) mxw_problem(S));
+  {
+    // all or nothing: the operator and factors (and the layout's device copy
+    // if this problem builds it) must fit the context's budget
+    const uint64_t need = problem_bytes(L, precision) + (S->on_device ? 0 : mirror_bytes(L));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->budget && ctx->in_use + need > ctx->budget) {
+      std::ostringstream os;
+      os << "problem needs " << need << " device bytes, " << ctx->in_use << " in use, budget " << ctx->budget;
+      set_error(os.str());
+      return MXW_ENOMEM;
+    }
+  }
+  TRY(ensure_device_layout(*S, ctx, st));
+  std::unique_ptr<mxw_problem> P(new (std::nothrow) mxw_problem(S, ctx, st));
   if (!P) {
     set_error("host allocation failed");
     return MXW_ENOMEM;
@@ -987,8 +1300,9 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
   P->lu_scratch = M.alloc<unsigned char>((size_t)L.sum_ns * 2 * kLuNB * rsz);
   P->AT = M.alloc<double2>((size_t)L.nt * nloc * nloc);
   P->vals = M.alloc<double2>(L.cols.size());
+  P->sub_list = M.alloc<int>(L.n_sub);
   if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->vals || !P->eps || !P->imp_beta ||
-      !P->imp_eps || !P->sub_face_coef) {
+      !P->imp_eps || !P->sub_face_coef || !P->sub_list) {
     set_error("device allocation failed (factors or element data)");
     return MXW_ENOMEM;
   }
@@ -1008,10 +1322,11 @@ mxw_status create_problem(const std::shared_ptr<LayoutShared>& S, const double* 
 // ---------------------------------------------------------------------------
 // block FGMRES (one Krylov space shared by the p right-hand sides)
 // ---------------------------------------------------------------------------
-constexpr int kMaxGramParts = 128;   // split-K partial products of a Gram matrix
-
-mxw_status ensure_block_ws(BlockWork& b, int64_t n, int p, int m) {
-  if (b.p == p && b.m == m && b.ndof == n && b.H1) return MXW_OK;
+// with_xi: also the interleaved copy of a block for products with A (block
+// GMRES with p >= kIlMinCols)
+mxw_status ensure_block_ws(BlockWork& b, int64_t n, int p, int m, bool with_xi = false) {
+  const bool want_xi = with_xi && p >= kIlMinCols;
+  if (b.p == p && b.m == m && b.ndof == n && b.H1 && (b.Xi != nullptr) == want_xi) return MXW_OK;
   b.mem.reset();
   b.p = p;
   b.m = m;
@@ -1035,16 +1350,17 @@ mxw_status ensure_block_ws(BlockWork& b, int64_t n, int p, int m) {
   b.Y = b.mem.alloc<double2>((size_t)m * p * p);
   b.est = b.mem.alloc<double>(p);
   b.info = b.mem.alloc<int>(2);
+  b.Xi = want_xi ? b.mem.alloc<double2>((size_t)n * interleaved_cols()) : nullptr;
   if (!b.H1 || !b.H2 || !b.Hc || !b.part || !b.G || !b.G0 || !b.R1 || !b.R1i || !b.R2 || !b.R2i || !b.S || !b.T || !b.Rls ||
-      !b.E || !b.Y || !b.est || !b.info) {
+      !b.E || !b.Y || !b.est || !b.info || (want_xi && !b.Xi)) {
     b.H1 = nullptr;
-    set_error("block Krylov workspace allocation failed");
+    set_error("block Krylov workspace: " + b.mem.why);
     return MXW_ENOMEM;
   }
   return MXW_OK;
 }
 
-mxw_status ensure_block(mxw_problem* P, int p, int m) { return ensure_block_ws(P->bw, P->L.ndof, p, m); }
+mxw_status ensure_block(mxw_problem* P, int p, int m) { return ensure_block_ws(P->bw, P->L.ndof, p, m, true); }
 
 // out (Q x p, column-major) = A^H W, A: Q vectors of length n, W: p vectors,
 // as split-K partial products summed in a fixed order
@@ -1083,6 +1399,18 @@ mxw_status cholqr2(mxw_problem* P, BlockWork& b, hipStream_t st, const double2* 
   launch_chol(st, p, b.G, b.R2, b.R2i, b.R1, b.S, b.info);
   TRY(tall_gemm(P, st, tmp, p, b.R2i, p, p, 1.0, 0.0, out));
   return MXW_OK;
+}
+
+// y = A x (b != nullptr: y = b - A x) for the p columns of a block (stride
+// ndof): through the interleaved copy from kIlMinCols columns on (the matrix
+// read once), else the column-group product
+void block_spmv(mxw_problem* P, hipStream_t st, const double2* x, double2* y, const double2* b, int p) {
+  const int64_t n = P->L.ndof;
+  ScopedKernelTimer tm("spmv");
+  if (p >= kIlMinCols && P->bw.Xi)
+    launch_spmm_interleaved(st, n, p, P->rowptr, P->cols, P->vals, x, n, P->bw.Xi, y, n, b, n);
+  else
+    launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, x, n, y, n, b, n, p, nullptr);
 }
 
 mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_opts* opts, hipStream_t st,
@@ -1124,10 +1452,7 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
       double2* Zj = k.Z + (int64_t)j * p * n;
       const int Q = (j + 1) * p;
       apply_prec_dev(P, st, Vj, n, Zj, n, p, nullptr, k.YS, k.xbuf);
-      {
-        ScopedKernelTimer tm("spmv");
-        launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, n, k.W, n, nullptr, 0, p, nullptr);
-      }
+      block_spmv(P, st, Zj, k.W, nullptr, p);
       // block classical Gram-Schmidt; a second pass where a column lost more
       // than 1 - 1/sqrt(2) of its norm in the first
       TRY(gram(P, st, k.W, p, k.W, p, b.G0));
@@ -1193,7 +1518,7 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
       }
     }
     TRY(tall_gemm(P, st, k.Z, jd * p, b.Y, m * p, p, 1.0, 1.0, X));
-    spmv_dev(P, st, X, k.Rv, B, p, nullptr);
+    block_spmv(P, st, X, k.Rv, B, p);
     launch_norm(st, n, k.Rv, n, k.npart, k.beta, p, nullptr);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipMemcpyAsync(hbuf, k.beta, sizeof(double) * p, hipMemcpyDeviceToHost, st));
@@ -1477,7 +1802,7 @@ mxw_status recycle_solve_one(mxw_problem* P, hipStream_t st, const double2* b, d
 
 extern "C" {
 
-mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64_t hbm_budget, int32_t defer_factor,
+mxw_status mxw_problem_create(mxw_ctx* ctx, const mxw_problem_desc* desc, void* stream, int32_t defer_factor,
                               mxw_problem** out) {
   if (!out) {
     set_error("out is NULL");
@@ -1492,20 +1817,20 @@ mxw_status mxw_problem_create(const mxw_problem_desc* desc, void* stream, uint64
     set_error("host allocation failed");
     return MXW_ENOMEM;
   }
-  return create_problem(S, nullptr, S->L.k0, desc->precision, desc->prec_variant, (hipStream_t)stream, hbm_budget,
+  return create_problem(ctx_of(ctx), S, nullptr, S->L.k0, desc->precision, desc->prec_variant, (hipStream_t)stream,
                         defer_factor, out);
 }
 
-mxw_status mxw_problem_create_from_layout(const mxw_layout* layout, const double* eps, double k0, int32_t precision,
-                                          int32_t prec_variant, void* stream, uint64_t hbm_budget,
+mxw_status mxw_problem_create_from_layout(mxw_ctx* ctx, const mxw_layout* layout, const double* eps, double k0,
+                                          int32_t precision, int32_t prec_variant, void* stream,
                                           int32_t defer_factor, mxw_problem** out) {
   if (!out || !layout) {
     set_error("NULL argument");
     return MXW_EINVAL;
   }
   *out = nullptr;
-  return create_problem(layout->S, eps, k0 < 0 ? layout->S->L.k0 : k0, precision, prec_variant,
-                        (hipStream_t)stream, hbm_budget, defer_factor, out);
+  return create_problem(ctx_of(ctx), layout->S, eps, k0 < 0 ? layout->S->L.k0 : k0, precision, prec_variant,
+                        (hipStream_t)stream, defer_factor, out);
 }
 
 mxw_status mxw_problem_set_medium(mxw_problem* prob, const double* eps, double k0, void* stream) {
@@ -1522,14 +1847,20 @@ mxw_status mxw_problem_set_medium(mxw_problem* prob, const double* eps, double k
       set_error("non-finite permittivity");
       return MXW_EINVAL;
     }
+  std::lock_guard<std::mutex> hold(prob->run);   // not while a solve uses the operator
   return assemble_medium(prob, eps, k0, (hipStream_t)stream, 0);
 }
 
 void mxw_problem_destroy(mxw_problem* prob) {
   if (!prob) return;
+  { std::lock_guard<std::mutex> lk(prob->run); }   // an asynchronous solve still running ends first
+  int cur = -1;
+  const int dev = prob->device;
+  const bool switched = hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess;
   release_timing_events();   // waits only on recorded timing events, if any
   if (prob->kw.host) hipHostFree(prob->kw.host);
   delete prob;
+  if (switched) hipSetDevice(cur);
 }
 
 mxw_status mxw_problem_get_info(const mxw_problem* prob, mxw_layout_info* info) {
@@ -1590,7 +1921,15 @@ mxw_status mxw_problem_export_local(const mxw_problem* prob, int32_t s, double* 
   return MXW_OK;
 }
 
-mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Right-hand sides of mxw_problem_rhs.  given_work: a device buffer of at
+// least n_imp_faces * nfloc complex128 for the face integrals of plane-wave
+// and port sources (nullptr: allocated here when a source needs it).
+mxw_status rhs_impl(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev, void* stream,
+                    double2* given_work) {
   TRY(check_problem(prob));
   if (nrhs < 0 || (nrhs > 0 && (!src || !b_dev))) {
     set_error("invalid argument");
@@ -1601,7 +1940,17 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
   const int64_t n = L.ndof;
   double2* b = (double2*)b_dev;
   HIP_CHECK(hipMemsetAsync(b, 0, sizeof(double2) * n * nrhs, st));
-  double2* work = nullptr;
+  double2* work = given_work;
+  DevMem tmp(prob->ctx, st);   // the face integrals, if a source needs them and none were given
+  auto face_work = [&]() -> mxw_status {
+    if (work) return MXW_OK;
+    work = tmp.alloc<double2>(L.imp_ft.size() * (size_t)L.basis.nfloc);
+    if (!work) {
+      set_error(tmp.why);
+      return MXW_ENOMEM;
+    }
+    return MXW_OK;
+  };
   for (int c = 0; c < nrhs; ++c) {
     const mxw_source& S = src[c];
     if (S.kind == MXW_SRC_DIPOLE) {
@@ -1643,9 +1992,7 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
       launch_rhs_dipole(st, prob->xyz, prob->tets, prob->tet_dofs, prob->phi, L.basis.nloc, found, lam, S.pol_re,
                         S.pol_im, b + (int64_t)c * n);
     } else if (S.kind == MXW_SRC_PLANEWAVE) {
-      if (!work) {
-        HIP_CHECK(hipMallocAsync((void**)&work, sizeof(double2) * std::max<size_t>(1, L.imp_ft.size() * L.basis.nfloc), st));
-      }
+      TRY(face_work());
       PlaneWaveArgs pa{(int)L.imp_ft.size(), n, prob->xyz, prob->ft_vert, prob->imp_ft, prob->imp_opp, prob->imp_beta,
                        prob->imp_eps, prob->fphi, L.basis.nfloc, prob->k0, prob->nq, prob->gx, prob->gw, prob->dof_ent,
                        prob->ent_imp_ptr, prob->ent_imps, prob->ft_dofs};
@@ -1653,9 +2000,7 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
     } else if (S.kind == MXW_SRC_PORT) {
       PortFrame pf;
       TRY(port_frame(S, pf));
-      if (!work) {
-        HIP_CHECK(hipMallocAsync((void**)&work, sizeof(double2) * std::max<size_t>(1, L.imp_ft.size() * L.basis.nfloc), st));
-      }
+      TRY(face_work());
       PlaneWaveArgs pa{(int)L.imp_ft.size(), n, prob->xyz, prob->ft_vert, prob->imp_ft, prob->imp_opp, prob->imp_beta,
                        prob->imp_eps, prob->fphi, L.basis.nfloc, prob->k0, prob->nq, prob->gx, prob->gw, prob->dof_ent,
                        prob->ent_imp_ptr, prob->ent_imps, prob->ft_dofs};
@@ -1666,9 +2011,72 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
     }
   }
   HIP_CHECK(hipGetLastError());
-  if (work) HIP_CHECK(hipFreeAsync(work, st));
-  HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipStreamSynchronize(st));   // before tmp goes back to the allocator
   return MXW_OK;
+}
+
+}  // namespace
+
+// The no-allocation variant's face-integral buffer: one copy per device,
+// held until the process ends.  Host code never passes `scratch` itself (on
+// the host it is only a stand-in for the symbol): it looks up the device
+// address once per device with hipGetSymbolAddress and uses that.
+constexpr size_t kRhsScratchElems = (size_t)1 << 18;   // 4 MiB of complex128
+static __device__ __align__(256) double2 scratch[kRhsScratchElems];
+
+namespace {
+
+static std::mutex g_scratch_mu;
+static std::map<int, double2*> g_scratch_ptr;
+
+mxw_status rhs_scratch(double2** out) {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    double2* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_error("no device address for the right-hand-side scratch buffer");
+      return MXW_EDEVICE;
+    }
+    it = g_scratch_ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return MXW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev, void* stream) {
+  return rhs_impl(prob, nrhs, src, b_dev, stream, nullptr);
+}
+
+mxw_status mxw_problem_rhs_noalloc(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev,
+                                   void* stream) {
+  TRY(check_problem(prob));
+  const size_t need = prob->L.imp_ft.size() * (size_t)prob->L.basis.nfloc;
+  if (need > kRhsScratchElems) {
+    std::ostringstream os;
+    os << "mxw_problem_rhs_noalloc: the face integrals need " << need * sizeof(double2)
+       << " bytes, more than the fixed " << kRhsScratchElems * sizeof(double2) << "-byte buffer";
+    set_error(os.str());
+    return MXW_EINVAL;
+  }
+  if (prob->device >= 0) {
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (dev != prob->device) {
+      set_error("mxw_problem_rhs_noalloc: the problem lives on another device than the current one");
+      return MXW_EINVAL;
+    }
+  }
+  double2* work = nullptr;
+  TRY(rhs_scratch(&work));
+  return rhs_impl(prob, nrhs, src, b_dev, stream, work);
 }
 
 mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_dev, double* y_dev, void* stream) {
@@ -1695,19 +2103,24 @@ mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double*
     return MXW_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
+  DevMem tmp(prob->ctx, st);
   double2* ys = nullptr;
   void* xbuf = nullptr;
-  if (gathered(prob->variant))
-    HIP_CHECK(hipMallocAsync((void**)&ys, sizeof(double2) * prob->L.sum_ns * std::max(1, nrhs), st));
+  if (gathered(prob->variant) && !(ys = tmp.alloc<double2>(prob->L.sum_ns * (size_t)std::max(1, nrhs)))) {
+    set_error(tmp.why);
+    return MXW_ENOMEM;
+  }
   if (!gathered(prob->variant) && nrhs >= 2) {
     const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
-    HIP_CHECK(hipMallocAsync(&xbuf, (size_t)nchunk * 2 * prob->L.sum_ns * multi_chunk_cols() * (prob->mixed ? 4 : 8), st));
+    xbuf = tmp.alloc<unsigned char>((size_t)nchunk * 2 * prob->L.sum_ns * multi_chunk_cols() * (prob->mixed ? 4 : 8));
+    if (!xbuf) {
+      set_error(tmp.why);
+      return MXW_ENOMEM;
+    }
   }
   apply_prec_dev(prob, st, (const double2*)v_dev, prob->L.ndof, (double2*)z_dev, prob->L.ndof, nrhs, nullptr, ys, xbuf);
   HIP_CHECK(hipGetLastError());
-  if (ys) HIP_CHECK(hipFreeAsync(ys, st));
-  if (xbuf) HIP_CHECK(hipFreeAsync(xbuf, st));
-  HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipStreamSynchronize(st));   // before tmp goes back to the allocator
   return MXW_OK;
 }
 
@@ -1730,6 +2143,7 @@ mxw_status mxw_solve_rhs(mxw_problem* P, int32_t nrhs, const double* b_dev, cons
     set_error("problem is not factorised");
     return MXW_EINVAL;
   }
+  std::lock_guard<std::mutex> hold(P->run);   // the Krylov workspace is the problem's
   if (opts->krylov == MXW_KRYLOV_BLOCK) {
     if (nrhs > max_block_p()) {
       set_error("block GMRES takes at most 32 right-hand sides per block");
@@ -1906,13 +2320,11 @@ mxw_status mxw_solve(mxw_problem* P, int32_t nrhs, const mxw_source* src, const 
   }
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = P->L.ndof;
-  double2 *b = nullptr, *x = nullptr;
-  HIP_CHECK(hipMalloc((void**)&b, sizeof(double2) * n * nrhs));
-  if (E_out_is_device)
-    x = (double2*)E_out;
-  else if (hipMalloc((void**)&x, sizeof(double2) * n * nrhs) != hipSuccess) {
-    hipFree(b);
-    set_error("device allocation failed");
+  DevMem tmp(P->ctx, st);
+  double2* b = tmp.alloc<double2>((size_t)n * nrhs);
+  double2* x = E_out_is_device ? (double2*)E_out : (b ? tmp.alloc<double2>((size_t)n * nrhs) : nullptr);
+  if (!b || !x) {
+    set_error(tmp.why);
     return MXW_ENOMEM;
   }
   mxw_status s = mxw_problem_rhs(P, nrhs, src, (double*)b, stream);
@@ -1921,9 +2333,101 @@ mxw_status mxw_solve(mxw_problem* P, int32_t nrhs, const mxw_source* src, const 
     hipMemcpyAsync(E_out, x, sizeof(double2) * n * nrhs, hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
   }
-  hipFree(b);
-  if (!E_out_is_device) hipFree(x);
+  hipStreamSynchronize(st);   // before tmp goes back to the allocator
   return s;
+}
+
+}  // extern "C"
+
+struct mxw_ticket {
+  std::thread th;
+  std::atomic<int> done{0};
+  mxw_status status = MXW_OK;
+  std::string msg;
+  std::vector<mxw_source> src;
+  mxw_solve_opts opts{};
+};
+
+extern "C" {
+
+mxw_status mxw_solve_async(mxw_problem* P, int32_t nrhs, const mxw_source* src, const mxw_solve_opts* opts,
+                           void* stream, double* E_out, int32_t E_out_is_device, int32_t* iters_out,
+                           double* relres_out, mxw_ticket** ticket) {
+  TRY(check_problem(P));
+  if (!ticket || nrhs < 1 || !src || !opts || !E_out) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  *ticket = nullptr;
+  std::unique_ptr<mxw_ticket> T(new (std::nothrow) mxw_ticket());
+  if (!T) {
+    set_error("host allocation failed");
+    return MXW_ENOMEM;
+  }
+  T->src.assign(src, src + nrhs);
+  T->opts = *opts;
+  mxw_ticket* t = T.get();
+  const int dev = P->device;
+  try {
+    T->th = std::thread([=] {
+      mxw_status st = (hipSetDevice(dev) == hipSuccess)
+                          ? mxw_solve(P, nrhs, t->src.data(), &t->opts, stream, E_out, E_out_is_device, iters_out,
+                                      relres_out)
+                          : dev_fail("hipSetDevice", hipGetLastError());
+      t->status = st;
+      if (st != MXW_OK) t->msg = g_err;
+      t->done.store(1, std::memory_order_release);
+    });
+  } catch (const std::system_error&) {
+    set_error("could not start the solve thread");
+    return MXW_ENOMEM;
+  }
+  *ticket = T.release();
+  return MXW_OK;
+}
+
+mxw_status mxw_ticket_poll(mxw_ticket* t, int32_t* done) {
+  if (!t || !done) {
+    set_error("invalid argument");
+    return MXW_EINVAL;
+  }
+  *done = t->done.load(std::memory_order_acquire);
+  return MXW_OK;
+}
+
+mxw_status mxw_ticket_wait(mxw_ticket* t) {
+  if (!t) {
+    set_error("ticket is NULL");
+    return MXW_EINVAL;
+  }
+  if (t->th.joinable()) t->th.join();
+  if (t->status != MXW_OK) set_error(t->msg);
+  return t->status;
+}
+
+void mxw_ticket_destroy(mxw_ticket* t) {
+  if (!t) return;
+  if (t->th.joinable()) t->th.join();
+  delete t;
+}
+
+mxw_status mxw_problem_factor_stats(const mxw_problem* P, int32_t* refactored_last, int64_t* refactored_total,
+                                    int64_t* kept_total) {
+  TRY(check_problem(P));
+  if (refactored_last) *refactored_last = (int32_t)P->refactor_last;
+  if (refactored_total) *refactored_total = P->refactor_total;
+  if (kept_total) *kept_total = P->kept_total;
+  return MXW_OK;
+}
+
+mxw_status mxw_problem_device_bytes(const mxw_problem* P, uint64_t* bytes) {
+  TRY(check_problem(P));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return MXW_EINVAL;
+  }
+  *bytes = P->mem.bytes + P->kw.mem.bytes + P->bw.mem.bytes + P->rw.mem.bytes + P->rw.bw.mem.bytes;
+  return MXW_OK;
 }
 
 mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku,
@@ -1942,6 +2446,7 @@ mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t mul
   if (lu_ku) P->lu_ku = lu_ku;
   if (multi_rows) P->multi_rows = multi_rows;
   if (P->multi_rows == 128) P->multi_ku = 8;   // 128-row passes take 8-wide slices
+  P->kw.drop_graphs();   // captured steps hold the previous tile kernels
   return MXW_OK;
 }
 
@@ -1953,7 +2458,7 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
   }
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = P->L.ndof;
-  DevMem tmp;
+  DevMem tmp(P->ctx, st);
   double2* x = tmp.alloc<double2>((size_t)n * nrhs);
   double2* y = tmp.alloc<double2>((size_t)n * nrhs);
   if (!x || !y) {
@@ -2049,6 +2554,7 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
     }
   }
   t.lu_ku = P->mixed ? P->lu_ku : 4;
+  P->kw.drop_graphs();   // captured steps hold the previous tile kernels
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));
   if (out) *out = t;
@@ -2069,13 +2575,14 @@ mxw_status mxw_smatrix(mxw_problem* P, int32_t nports, const mxw_source* ports, 
   const int64_t n = L.ndof;
   const int nimp = (int)L.imp_ft.size();
   constexpr int kChunk = 32;
-  DevMem tmp;
+  DevMem tmp(P->ctx, st);
   double2* W = tmp.alloc<double2>((size_t)kChunk * n);
   double2* work = tmp.alloc<double2>(std::max<size_t>(1, (size_t)nimp * L.basis.nfloc));
   double* fnorm = tmp.alloc<double>(std::max(1, nimp));
   double* den = tmp.alloc<double>(kChunk);
   double2* num = tmp.alloc<double2>((size_t)kChunk * nsol);
   BlockWork bw;
+  bw.mem.ctx = P->ctx;
   if (!W || !work || !fnorm || !den || !num || ensure_block_ws(bw, n, kChunk, (nsol + kChunk - 1) / kChunk + 1) != MXW_OK) {
     set_error("device allocation failed (S-matrix buffers)");
     return MXW_ENOMEM;
@@ -2125,6 +2632,7 @@ mxw_status mxw_solve_recycle(mxw_problem* P, int32_t nrhs, const double* b_dev, 
     return MXW_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> hold(P->run);
   TRY(ensure_recycle(P, k, opts->restart));
   const int64_t n = P->L.ndof;
   mxw_status result = MXW_OK;

@@ -246,12 +246,25 @@ __global__ void __launch_bounds__(256) k_chol(int p, const double2* __restrict__
     A[r][c] = make_double2(G[idx].x * sc, G[idx].y * sc);
   }
   __syncthreads();
+  // A floored pivot marks a column that depends on the ones before it: its
+  // row of R~ right of the diagonal is set to zero instead of being divided
+  // by the tiny pivot.  Dividing would put multipliers of size 1/sqrt(floor)
+  // into R~, and the back substitution for R~^-1 compounds them from one
+  // dependent column to the next (for a block with geometrically decaying
+  // singular values, R~^-1 reached 1e54 in a host model of this kernel, and
+  // the next Gram matrix overflows).  With the row zeroed R~^-1 stays bounded
+  // by 1/sqrt(floor); W = Q R still holds exactly (Q = W R^-1), the columns
+  // after k keep their small component along the dependent direction, and the
+  // second Cholesky QR pass orthogonalises them.
+  __shared__ int floored;
   const double floor_ = 1e-15 * p;
   for (int k = 0; k < p; ++k) {
     if (tid == 0) {
       double d = A[k][k].x;
+      floored = 0;
       if (!(d > floor_)) {
         bad = 1;
+        floored = 1;
         d = fmax(floor_, 1e-300);
       }
       A[k][k] = make_double2(sqrt(d), 0.0);
@@ -259,7 +272,8 @@ __global__ void __launch_bounds__(256) k_chol(int p, const double2* __restrict__
     __syncthreads();
     const double rkk = A[k][k].x;
     // row k right of the diagonal, then the trailing Hermitian update
-    for (int c = k + 1 + tid; c < p; c += 256) A[k][c] = make_double2(A[k][c].x / rkk, A[k][c].y / rkk);
+    for (int c = k + 1 + tid; c < p; c += 256)
+      A[k][c] = floored ? make_double2(0.0, 0.0) : make_double2(A[k][c].x / rkk, A[k][c].y / rkk);
     __syncthreads();
     for (int idx = tid; idx < p * p; idx += 256) {
       const int r = idx % p, c = idx / p;

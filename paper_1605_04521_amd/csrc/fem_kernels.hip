@@ -250,8 +250,8 @@ __global__ void __launch_bounds__(256) k_assemble_local(
     const int64_t* __restrict__ tet_ptr, const int* __restrict__ tets, const int* __restrict__ lmap,
     const double2* __restrict__ AT, int nloc, const int64_t* __restrict__ face_ptr,
     const int* __restrict__ face_ft, const double* __restrict__ face_coef, const int* __restrict__ face_lmap,
-    const double* __restrict__ BF, int nfloc, int with_ifaces) {
-  const int s = blockIdx.x;
+    const double* __restrict__ BF, int nfloc, int with_ifaces, const int* __restrict__ list) {
+  const int s = list ? list[blockIdx.x] : blockIdx.x;
   const int n = nsz[s], ld = lds[s];
   R* re = F + foff[s];
   R* im = re + (int64_t)ld * n;
@@ -610,7 +610,7 @@ void launch_assemble_local(hipStream_t st, const LocalAssembleArgs& a, R* F) {
   if (a.n_sub == 0) return;
   hipLaunchKernelGGL(k_assemble_local<R>, dim3(a.n_sub), dim3(256), 0, st, F, a.foff, a.nsz, a.lds, a.tet_ptr,
                      a.tets, a.lmap, a.AT, a.nloc, a.face_ptr, a.face_ft, a.face_coef, a.face_lmap, a.BF,
-                     a.nfloc, 1);
+                     a.nfloc, 1, a.list);
 }
 template void launch_assemble_local<double>(hipStream_t, const LocalAssembleArgs&, double*);
 template void launch_assemble_local<float>(hipStream_t, const LocalAssembleArgs&, float*);

@@ -67,6 +67,7 @@ struct LocalAssembleArgs {
   const int* face_lmap;
   const double* BF;
   int nfloc;
+  const int* list = nullptr;   // subdomains to assemble (n_sub of them); nullptr = 0 .. n_sub-1
 };
 template <typename R>
 void launch_assemble_local(hipStream_t st, const LocalAssembleArgs& a, R* F);
@@ -158,6 +159,14 @@ int max_block_p();
 void launch_spmv(hipStream_t st, int group, int64_t n, const int64_t* rowptr, const int* cols, const double2* vals,
                  const double2* x, int64_t xstride, double2* y, int64_t ystride, const double2* b, int64_t bstride,
                  int ncol, const int* active);
+
+// y = A x (or b - A x) for p <= interleaved_cols() columns through an
+// interleaved copy xi [n][interleaved_cols()] of x (scratch, written here);
+// the matrix is read once for all columns
+void launch_spmm_interleaved(hipStream_t st, int64_t n, int p, const int64_t* rowptr, const int* cols,
+                             const double2* vals, const double2* x, int64_t xstride, double2* xi, double2* y,
+                             int64_t ystride, const double2* b, int64_t bstride);
+int interleaved_cols();
 
 int red_blocks(int64_t ndof);
 void launch_dots(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64_t vcol, const double2* w,

@@ -327,6 +327,81 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
   }
 }
 
+// Block of right-hand sides given interleaved (xi[j * kIlCols + c], column c
+// of unknown j): a half-wave of 32 lanes owns a row and one column per lane,
+// so every gather of x reads the 512 contiguous bytes of one unknown's
+// columns and the matrix is read once for all of them.  Each lane sums its
+// column over the row's entries in order (a different summation order from
+// k_spmv).  The 32 x 32 result tile of a block goes through LDS so that the
+// column-major output is written in 512-byte runs.
+constexpr int kIlCols = 32;
+constexpr int kIlRows = 32;   // rows per workgroup
+__global__ void __launch_bounds__(256) k_spmm_il(int64_t n, int p, const int64_t* __restrict__ rowptr,
+                                                 const int* __restrict__ cols, const double2* __restrict__ vals,
+                                                 const double2* __restrict__ xi, double2* __restrict__ y,
+                                                 int64_t ystride, const double2* __restrict__ b, int64_t bstride) {
+  __shared__ double2 tile[kIlRows][kIlCols + 1];
+  const int lane = threadIdx.x & 31;
+  const int sub = threadIdx.x >> 5;   // 8 half-waves
+  const int64_t row0 = (int64_t)blockIdx.x * kIlRows;
+  for (int rr = sub; rr < kIlRows; rr += 8) {
+    const int64_t row = row0 + rr;
+    double sr = 0.0, si = 0.0;
+    if (row < n) {
+      const int64_t r0 = rowptr[row], r1 = rowptr[row + 1];
+      for (int64_t e = r0; e < r1; e += 4) {
+        int ci[4];
+        double2 a[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = e + u < r1;
+          ci[u] = ok ? cols[e + u] : 0;
+          a[u] = ok ? vals[e + u] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = xi[(int64_t)ci[u] * kIlCols + lane];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          sr += a[u].x * xv[u].x - a[u].y * xv[u].y;
+          si += a[u].x * xv[u].y + a[u].y * xv[u].x;
+        }
+      }
+    }
+    tile[rr][lane] = make_double2(sr, si);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kIlRows * kIlCols; idx += 256) {
+    const int c = idx / kIlRows, r = idx % kIlRows;
+    const int64_t row = row0 + r;
+    if (row >= n || c >= p) continue;
+    double2 v = tile[r][c];
+    if (b) {
+      const double2 bv = b[(int64_t)c * bstride + row];
+      v = make_double2(bv.x - v.x, bv.y - v.y);
+    }
+    y[(int64_t)c * ystride + row] = v;
+  }
+}
+
+// xi[j * kIlCols + c] = x[c * xstride + j] for c < p, and 0 for p <= c < 32
+// (every lane of k_spmm_il reads its column; unused ones must be finite)
+__global__ void __launch_bounds__(256) k_to_interleaved(int64_t n, int p, const double2* __restrict__ x,
+                                                        int64_t xstride, double2* __restrict__ xi) {
+  __shared__ double2 tile[kIlCols][kIlRows + 1];
+  const int64_t j0 = (int64_t)blockIdx.x * kIlRows;
+  for (int idx = threadIdx.x; idx < kIlCols * kIlRows; idx += 256) {
+    const int c = idx / kIlRows, r = idx % kIlRows;   // reads along j for one column
+    const int64_t j = j0 + r;
+    tile[c][r] = (j < n && c < p) ? x[(int64_t)c * xstride + j] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kIlCols * kIlRows; idx += 256) {
+    const int r = idx / kIlCols, c = idx % kIlCols;   // writes along c for one unknown
+    const int64_t j = j0 + r;
+    if (j < n) xi[j * kIlCols + c] = tile[c][r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Krylov vector kernels.  Column c of the batch uses V + c*vcol, where
 // vector i of the basis is at offset i*ndof.
@@ -607,6 +682,17 @@ void launch_spmv(hipStream_t st, int group, int64_t n, const int64_t* rowptr, co
     default: spmv_g<32>(st, nb, n, rowptr, cols, vals, x, xstride, y, ystride, b, bstride, ncol, active); break;
   }
 }
+
+void launch_spmm_interleaved(hipStream_t st, int64_t n, int p, const int64_t* rowptr, const int* cols,
+                             const double2* vals, const double2* x, int64_t xstride, double2* xi, double2* y,
+                             int64_t ystride, const double2* b, int64_t bstride) {
+  if (n == 0 || p == 0) return;
+  const unsigned nb = (unsigned)((n + kIlRows - 1) / kIlRows);
+  hipLaunchKernelGGL(k_to_interleaved, dim3(nb), dim3(256), 0, st, n, p, x, xstride, xi);
+  timed_launch(k_spmm_il, dim3(nb), dim3(256), 0, st, n, p, rowptr, cols, vals, xi, y, ystride, b, bstride);
+}
+
+int interleaved_cols() { return kIlCols; }
 
 int red_blocks(int64_t ndof) { return (int)((ndof + kChunk - 1) / kChunk); }
 

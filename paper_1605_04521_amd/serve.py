@@ -2,25 +2,30 @@
 
 An imaging inversion issues forward solves one after another, each with its
 own permittivity map and a set of transmitting antennas (right-hand sides),
-often on a handful of meshes.  The loop:
+often on a handful of meshes, and with media that differ mostly inside the
+imaged head (Sec. 6: slowly varying systems).  The loop:
 
 * admits a request when a slot is free and its device memory fits the HBM
-  budget: a resident idle problem for the same mesh costs nothing, a new one
-  costs its footprint; idle problems of other meshes are evicted (least
-  recently used first) to make room.  Admission is re-evaluated at every
-  arrival and every completion, so requests that arrive while others run
-  start as soon as memory and a slot free up;
+  budget.  A new problem is charged its exact footprint (operator, factors,
+  Krylov workspace for the request's sources, solve temporaries, plus the
+  mesh's shared device copy the first time); a resident idle problem on the
+  same mesh is charged only what the request needs beyond the bytes it
+  already holds (a larger source count grows its Krylov workspace).  Idle
+  problems are evicted, least recently used first, to make room.  Admission
+  is re-evaluated at every arrival and every completion;
 * keeps problems (device operator, LU factors, Krylov workspace) resident per
-  mesh: a request whose medium equals the resident one reuses the factors
-  outright; otherwise the resident problem is re-assembled and re-factorised
-  in place (no device allocation);
-* runs every admitted request on its own HIP stream in a worker thread, so the
-  kernels of concurrent requests overlap on the device; all right-hand sides of
-  a request are solved together (block GMRES, one Krylov space per request);
-* records arrival, start and completion times.
+  mesh: a request with the resident medium reuses every factor; a new medium
+  is assembled in place and only the subdomains whose local data changed are
+  factorised again (the library keeps the others);
+* runs every admitted request's solve as an asynchronous library call (a
+  ticket) on its own HIP stream, so the kernels of concurrent requests overlap
+  on the device; all right-hand sides of a request share one block Krylov
+  space (at most 32 of them);
+* records arrival, start and completion times and, once a request has
+  finished, corrects the budget with the bytes its problem really holds.
 
-The scheduling core (`Scheduler`) does not touch the GPU, so it is tested on
-the CPU with a fake backend.
+The scheduling core (`Scheduler`, `Server`) does not touch the GPU, so it is
+tested on the CPU with a fake backend.
 """
 from __future__ import annotations
 
@@ -28,7 +33,7 @@ import hashlib
 import heapq
 import threading
 import time
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 
@@ -48,7 +53,8 @@ class Request:
     iters: object = None
     relres: object = None
     error: str = None
-    reused: str = ""             # "factors", "buffers" or "new"
+    reused: str = ""             # "factors" (same medium), "partial" (new medium, some factors kept) or "new"
+    refactored: tuple = None     # (subdomains factorised for this request, subdomains)
 
 
 def medium_key(eps: np.ndarray, k0: float) -> str:
@@ -58,10 +64,22 @@ def medium_key(eps: np.ndarray, k0: float) -> str:
 
 
 @dataclass
+class Resident:
+    """A problem kept on the device between requests."""
+    mesh: str
+    precision: int
+    key: str                     # medium key its factors were made for
+    problem: object
+    held: int                    # device bytes it holds (operator, factors, workspaces)
+    last_use: int = 0
+
+
+@dataclass
 class Plan:
-    kind: str            # "reuse" or "new"
-    handle: object = None
-    nbytes: int = 0
+    kind: str                    # "reuse" or "new"
+    entry: Resident = None       # the idle problem to reuse
+    nbytes: int = 0              # bytes to reserve on admission
+    copy_bytes: int = 0          # part of nbytes that is the mesh's shared device copy
 
 
 class Scheduler:
@@ -84,13 +102,14 @@ class Scheduler:
         while self.waiting and self.running < self.slots:
             req = self.waiting[0][2]
             plan = self.backend.plan(req)
-            if plan.kind == "new":
-                over = self.backend.allocated + plan.nbytes - self.budget
-                if over > 0:
-                    self.backend.evict_idle(over)
-                if self.backend.allocated + plan.nbytes > self.budget:
-                    break                          # wait for a completion
-                self.backend.allocated += plan.nbytes   # reserved
+            over = self.backend.allocated + plan.nbytes - self.budget
+            if over > 0:
+                self.backend.evict_idle(over, keep=plan.entry)
+            if self.backend.allocated + plan.nbytes > self.budget:
+                break                              # wait for a completion
+            self.backend.take(plan)
+            self.backend.allocated += plan.nbytes  # reserved
+            self.backend.max_allocated = max(self.backend.max_allocated, self.backend.allocated)
             heapq.heappop(self.waiting)
             self.running += 1
             out.append((req, plan))
@@ -101,97 +120,143 @@ class Scheduler:
 
 
 class GpuBackend:
-    """Resident problems per mesh on one GPU (one catalogue of layouts)."""
+    """Resident problems per mesh on one GPU, all allocated through one
+    library context whose budget is the loop's (the library refuses what
+    admission would have let through by mistake)."""
 
-    def __init__(self, catalogue):
-        from .api import Layout
+    def __init__(self, catalogue, budget: int = 0, slots: int = 4):
+        import torch
+        from .api import Context, Layout
         self.catalogue = catalogue       # mesh key -> gen.Problem (mesh, partition, k0, degree)
         self.layouts = {k: Layout.from_problem(p) for k, p in catalogue.items()}
-        self.idle = []                   # (last use, mesh, precision, medium key, problem, nbytes)
+        self.ctx = Context(budget=budget)
+        self.idle = []                   # Resident
+        self.copies = set()              # meshes whose shared device copy is counted
         self.allocated = 0
+        self.max_allocated = 0
         self.lock = threading.Lock()
         self.clock = 0
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, slots))]
+        self.free_streams = list(self.streams)
+
+    @staticmethod
+    def _krylov(req):
+        from . import _lib as B
+        return B.MXW_KRYLOV_BLOCK if len(req.sources) <= 32 else B.MXW_KRYLOV_PSEUDOBLOCK
+
+    def need(self, req) -> int:
+        """Bytes of a problem for this request, without the mesh's copy."""
+        return self.layouts[req.mesh].footprint(req.precision, len(req.sources), krylov=self._krylov(req),
+                                                with_layout_copy=False)
+
+    def temp_bytes(self, req) -> int:
+        """The solve's temporaries inside need(req): right-hand sides, the
+        solution, face integrals (see mxw_layout_footprint)."""
+        info = self.layouts[req.mesh].info()
+        nfloc = {1: 3, 2: 8, 3: 15}[self.catalogue[req.mesh].degree]
+        return 2 * 16 * info.ndof * len(req.sources) + 16 * max(1, info.n_imp_faces * nfloc)
+
+    def copy_bytes(self, mesh) -> int:
+        lay = self.layouts[mesh]
+        return lay.footprint(0, 1) - lay.footprint(0, 1, with_layout_copy=False)
 
     def footprint(self, req) -> int:
-        return self.layouts[req.mesh].footprint(req.precision, len(req.sources))
+        return self.need(req) + self.copy_bytes(req.mesh)
 
     def plan(self, req) -> Plan:
         key = medium_key(req.eps, self.catalogue[req.mesh].k0)
         with self.lock:
-            cand = [i for i, e in enumerate(self.idle) if e[1] == req.mesh and e[2] == req.precision]
-            same = [i for i in cand if self.idle[i][3] == key]
+            cand = [e for e in self.idle if e.mesh == req.mesh and e.precision == req.precision]
+            same = [e for e in cand if e.key == key]
             pick = same[0] if same else (cand[0] if cand else None)
-            if pick is None:
-                return Plan("new", nbytes=self.footprint(req))
-            e = self.idle.pop(pick)
-            return Plan("reuse", handle=e)
+        if pick is None:
+            copy = 0 if req.mesh in self.copies else self.copy_bytes(req.mesh)
+            return Plan("new", nbytes=self.need(req) + copy, copy_bytes=copy)
+        # what the resident problem lacks (a larger Krylov workspace), plus the
+        # solve's temporaries
+        temp = self.temp_bytes(req)
+        return Plan("reuse", entry=pick, nbytes=max(0, self.need(req) - temp - pick.held) + temp)
 
-    def evict_idle(self, nbytes: int) -> int:
+    def take(self, plan: Plan):
+        with self.lock:
+            if plan.entry is not None:
+                self.idle.remove(plan.entry)
+
+    def evict_idle(self, nbytes: int, keep=None) -> int:
         freed = 0
         with self.lock:
-            self.idle.sort(key=lambda e: e[0])
-            while self.idle and freed < nbytes:
-                e = self.idle.pop(0)
-                e[4].close()
-                freed += e[5]
-                self.allocated -= e[5]
+            self.idle.sort(key=lambda e: e.last_use)
+            for e in [e for e in self.idle if e is not keep]:
+                if freed >= nbytes:
+                    break
+                self.idle.remove(e)
+                e.problem.close()
+                freed += e.held
+                self.allocated -= e.held
         return freed
 
-    def run(self, req, plan: Plan):
-        """Acquire (reuse / re-factorise / create), solve, return to the pool."""
-        import torch
-        from . import _lib as B
+    def start(self, req, run: dict):
+        """Acquire the problem (reuse, new medium in place, or create) and start
+        the request's solve as a ticket on a stream of its own.  run (made by
+        the server with the plan) records what was acquired, also when this
+        raises."""
         from .api import Problem
+        plan = run["plan"]
         base = self.catalogue[req.mesh]
         key = medium_key(req.eps, base.k0)
-        if plan.kind == "reuse":
-            _, _, _, mkey, P, nbytes = plan.handle
-            if mkey == key:
+        run["key"] = key
+        if plan.kind == "new":
+            self.copies.add(req.mesh)
+            run["P"] = Problem.from_layout(self.layouts[req.mesh], eps=req.eps, k0=base.k0,
+                                           precision=req.precision, ctx=self.ctx)
+            req.reused = "new"
+            n_sub = base.n_sub
+            req.refactored = (n_sub, n_sub)
+        else:
+            P = plan.entry.problem
+            run["P"], run["old"] = P, plan.entry.held
+            if plan.entry.key == key:
                 req.reused = "factors"
+                req.refactored = (0, base.n_sub)
             else:
                 P.set_medium(req.eps, base.k0)
-                req.reused = "buffers"
-        else:
-            nbytes = plan.nbytes
-            req.reused = "new"
-            P = Problem.from_layout(self.layouts[req.mesh], eps=req.eps, k0=base.k0, precision=req.precision)
-        try:
-            # one shared block Krylov space for the request's sources (at most
-            # 32; the block method needs fewer steps than one space per source)
-            krylov = B.MXW_KRYLOV_BLOCK if len(req.sources) <= 32 else B.MXW_KRYLOV_PSEUDOBLOCK
-            x, it, rr, st = P.solve(req.sources, allow_notconv=True, krylov=krylov)
-            torch.cuda.current_stream().synchronize()
-            req.result, req.iters, req.relres = x.cpu().numpy(), it, rr
-        finally:
-            with self.lock:
+                req.reused = "partial"
+                req.refactored = (P.factor_stats()["refactored_last"], base.n_sub)
+        run["stream"] = self.free_streams.pop() if self.free_streams else self.streams[0]
+        run["ticket"] = run["P"].solve_async(req.sources, krylov=self._krylov(req), stream=run["stream"])
+
+    def poll(self, run) -> bool:
+        return run["ticket"].done()
+
+    def release(self, req, run):
+        """Return the problem to the idle pool and settle the reservation with
+        the bytes it really holds now."""
+        P, plan = run.get("P"), run["plan"]
+        held = P.device_bytes() if P is not None else 0
+        with self.lock:
+            # the mesh copy stays counted (it lives as long as the layout)
+            self.allocated += held - run.get("old", 0) - (plan.nbytes - plan.copy_bytes)
+            if P is not None:
                 self.clock += 1
-                self.idle.append((self.clock, req.mesh, req.precision, key, P, nbytes))
+                key = run["key"] if req.error is None else ""     # a failed request's medium is not trusted
+                self.idle.append(Resident(req.mesh, req.precision, key, P, held, self.clock))
+        if run.get("stream") is not None and run["stream"] not in self.free_streams:
+            self.free_streams.append(run["stream"])
+
+    def finish(self, req, run):
+        x, it, rr, st = run["ticket"].wait(allow_notconv=True)
+        req.result, req.iters, req.relres = x.cpu().numpy(), it, rr
 
 
 class Server:
-    """Replays a request stream against a backend with continuous batching."""
+    """Replays a request stream against a backend with continuous batching:
+    one host loop admits requests, starts their solves asynchronously and
+    collects them as they complete."""
 
-    def __init__(self, backend, budget: int, slots: int = 4, use_streams: bool = True):
+    def __init__(self, backend, budget: int, slots: int = 4, poll_s: float = 0.002):
         self.backend = backend
         self.sched = Scheduler(backend, budget, slots)
-        self.use_streams = use_streams
-        self.cv = threading.Condition()
-
-    def _worker(self, req, plan, t0):
-        req.start = time.perf_counter() - t0
-        try:
-            if self.use_streams:
-                import torch
-                with torch.cuda.stream(torch.cuda.Stream()):
-                    self.backend.run(req, plan)
-            else:
-                self.backend.run(req, plan)
-        except Exception as e:     # one failing request must not stop the loop
-            req.error = repr(e)
-        req.finish = time.perf_counter() - t0
-        with self.cv:
-            self.sched.done()
-            self.cv.notify_all()
+        self.poll_s = poll_s
 
     def run(self, requests, realtime: bool = True):
         """Returns the wall time of the run."""
@@ -200,26 +265,43 @@ class Server:
         if not realtime:
             for r in pending:
                 r.arrival = 0.0
-        threads = []
+        running = []
         i = 0
-        with self.cv:
-            while True:
-                now = time.perf_counter() - t0
-                while i < len(pending) and pending[i].arrival <= now:
-                    self.sched.submit(pending[i])
-                    i += 1
-                for req, plan in self.sched.admit():
-                    th = threading.Thread(target=self._worker, args=(req, plan, t0), daemon=True)
-                    th.start()
-                    threads.append(th)
-                if i >= len(pending) and not self.sched.waiting and self.sched.running == 0:
-                    break
-                wait = 0.05
-                if i < len(pending):
-                    wait = min(wait, max(0.0, pending[i].arrival - (time.perf_counter() - t0)))
-                self.cv.wait(timeout=wait)
-        for th in threads:
-            th.join()
+        while True:
+            now = time.perf_counter() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                self.sched.submit(pending[i])
+                i += 1
+            for req, plan in self.sched.admit():
+                req.start = time.perf_counter() - t0
+                run = {"plan": plan}
+                try:
+                    self.backend.start(req, run)
+                    running.append((req, run))
+                except Exception as e:          # one failing request must not stop the loop
+                    req.error = repr(e)
+                    req.finish = time.perf_counter() - t0
+                    self.backend.release(req, run)
+                    self.sched.done()
+            still = []
+            for req, run in running:
+                if not self.backend.poll(run):
+                    still.append((req, run))
+                    continue
+                try:
+                    self.backend.finish(req, run)
+                except Exception as e:
+                    req.error = repr(e)
+                req.finish = time.perf_counter() - t0
+                self.backend.release(req, run)
+                self.sched.done()
+            running = still
+            if i >= len(pending) and not self.sched.waiting and not running:
+                break
+            wait = self.poll_s
+            if i < len(pending) and not running:
+                wait = max(wait, pending[i].arrival - (time.perf_counter() - t0))
+            time.sleep(min(wait, 0.05))
         return time.perf_counter() - t0
 
 

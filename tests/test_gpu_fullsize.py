@@ -131,3 +131,23 @@ def test_full_solve_true_residual(full):
     say(f"   iterations {it[0]} reported {rr[0]:.3e} true {true_rr:.3e}")
     assert rr[0] <= 1e-8 and true_rr <= 1.01e-8
     P.close()
+
+
+def test_full_block_mixed_restart30(full):
+    """Block FGMRES(30) on the batched benchmark's 32 dipoles with FP32 factors:
+    the residual block becomes numerically low-rank over the restarts, and the
+    Cholesky QR of a cycle's first block met floored pivots; it once ended in
+    non-finite values (MXW_EBREAKDOWN at the first step of the 12th cycle).
+    It must converge, with the true residuals of two sources recomputed with
+    the oracle's matrix and right-hand sides."""
+    prob, d, A = full
+    say("[gpu] full-size block FGMRES(30), 32 dipoles, FP32 factors")
+    P = Problem.from_problem(prob, precision=B.MXW_MIXED)
+    x, it, rr, st = P.solve(prob.sources, krylov=B.MXW_KRYLOV_BLOCK, restart=30, max_iters=1200)
+    say(f"   block steps {it[0]}, max relres {rr.max():.2e}")
+    assert st == B.MXW_OK and np.all(rr <= 1e-8)
+    x = x.cpu().numpy()
+    for c in (0, 17):
+        b = d.rhs(prob.sources[c])
+        assert np.linalg.norm(b - A @ x[c]) <= 1.01e-8 * np.linalg.norm(b), c
+    P.close()

@@ -209,20 +209,49 @@ def test_multi_column_local_solve(precision, ncol):
         assert np.linalg.norm(Zb[c] - z1) <= tol * np.linalg.norm(z1), c
 
 
-def test_set_medium_equals_fresh_problem():
-    prob = gen.chamber_problem(n=5, degree=2, n_sub=6, overlap=2, seed=1)
-    prob2 = gen.chamber_problem(n=5, degree=2, n_sub=6, overlap=2, seed=2)
-    say("[gpu] set_medium vs fresh problem")
-    P = Problem.from_problem(prob)
+@pytest.mark.parametrize("precision", [B.MXW_FP64, B.MXW_MIXED])
+def test_set_medium_equals_fresh_problem(precision):
+    """A new medium (another seeded head and inclusion in the same background)
+    re-factorises only the subdomains whose elements changed; the solution
+    equals a fresh problem's bit for bit, and a repeated medium keeps every
+    factor."""
+    prob = gen.chamber_problem(n=8, degree=2, n_sub=24, overlap=1, seed=1)
+    prob2 = gen.chamber_problem(n=8, degree=2, n_sub=24, overlap=1, seed=1)
+    # the medium changes inside a 3 cm ball in the head only
+    c = gen.centroids(prob.mesh)
+    sel = np.linalg.norm(c - np.array([0.02, 0.01, 0.12]), axis=1) < 0.03
+    prob2.eps = prob.eps.copy()
+    prob2.eps[sel] *= 1.05
+    say(f"[gpu] set_medium vs fresh problem precision={precision}")
+    P = Problem.from_problem(prob, precision=precision)
+    assert P.factor_stats()["refactored_last"] == prob.n_sub
     x1, it1, rr1, _ = P.solve(prob.sources[:1])
     P.set_medium(prob2.eps)
-    Q = Problem.from_problem(prob2)
+    st = P.factor_stats()
+    say(f"   re-factorised {st['refactored_last']} of {prob.n_sub} subdomains")
+    assert 0 < st["refactored_last"] < prob.n_sub
+    Q = Problem.from_problem(prob2, precision=precision)
     assert np.array_equal(P.matrix_values(), Q.matrix_values())
     xp, itp, _, _ = P.solve(prob2.sources[:1])
     xq, itq, _, _ = Q.solve(prob2.sources[:1])
     assert itp[0] == itq[0]
     assert np.array_equal(to_np(xp), to_np(xq))
     assert not np.allclose(to_np(x1), to_np(xp))
+    # the same medium again: nothing to re-factorise, same solution
+    P.set_medium(prob2.eps)
+    assert P.factor_stats()["refactored_last"] == 0
+    xr, itr, _, _ = P.solve(prob2.sources[:1])
+    assert np.array_equal(to_np(xr), to_np(xq))
+    # another seed moves the whole head: a new medium almost everywhere
+    prob3 = gen.chamber_problem(n=8, degree=2, n_sub=24, overlap=1, seed=2)
+    P.set_medium(prob3.eps)
+    Q3 = Problem.from_problem(prob3, precision=precision)
+    x3, _, _, _ = P.solve(prob3.sources[:1])
+    assert np.array_equal(to_np(x3), to_np(Q3.solve(prob3.sources[:1])[0]))
+    # RAS re-factorises every subdomain
+    R = Problem.from_problem(prob, precision=precision, variant=B.MXW_PREC_RAS)
+    R.set_medium(prob2.eps)
+    assert R.factor_stats()["refactored_last"] == prob.n_sub
 
 
 def test_oas_variant_converges_slower():
@@ -287,6 +316,12 @@ def test_graph_replay_matches_eager(nrhs):
     x1, it1, _, _ = P.solve_rhs(b[:1], restart=10, use_graph=1)
     x1e, it1e, _, _ = P.solve_rhs(b[:1], restart=10)
     assert np.array_equal(it1, it1e) and np.array_equal(to_np(x1), to_np(x1e))
+    # new tile choices between two replays: the graphs are captured again with
+    # the new kernels, and replay still equals the eager solve
+    P.set_tiles(spmv_group=4)
+    xg, itg, _, _ = P.solve_rhs(b, restart=10, use_graph=1)
+    xe2, ite2, _, _ = P.solve_rhs(b, restart=10)
+    assert np.array_equal(itg, ite2) and np.array_equal(to_np(xg), to_np(xe2))
 
 
 def test_multi_column_spmv():

@@ -90,6 +90,17 @@ def test_footprint_grows_with_rhs_and_precision():
     f32 = lay.footprint(B.MXW_FP64, 32)
     fm = lay.footprint(B.MXW_MIXED, 1)
     assert f32 > f1 > fm > 0
+    # a block solve adds its workspace; the layout copy is counted once
+    fb = lay.footprint(B.MXW_FP64, 32, krylov=B.MXW_KRYLOV_BLOCK)
+    assert fb > f32
+    assert 0 < f1 - lay.footprint(B.MXW_FP64, 1, with_layout_copy=False) < f1
+    # the standalone call (builds the layout itself) agrees with the layout's
+    prob = gen.chamber_problem(n=4, degree=2, n_sub=4, overlap=1)
+    from paper_1605_04521_amd.api import footprint
+    assert footprint(B.Desc.from_problem(prob, precision=B.MXW_FP64), 32) == f32
+    assert footprint(B.Desc.from_problem(prob, precision=B.MXW_MIXED), 1) == fm
+    # the gathered variants keep every local solution of a solve
+    assert lay.footprint(B.MXW_FP64, 1, variant=B.MXW_PREC_OAS) > f1
 
 
 def _desc_variant(**changes):
