@@ -259,6 +259,9 @@ mxw_status mxw_problem_create_from_layout(mxw_ctx* ctx, const mxw_layout* layout
  * last factorisation failed or was deferred redo every subdomain).  The
  * factors are the same bits as a fresh problem's for the new medium. */
 mxw_status mxw_problem_set_medium(mxw_problem* prob, const double* eps, double k0, void* stream);
+/* The next medium change re-assembles and factorises every subdomain, kept
+ * factors or not (a full factorisation, for instance to time it). */
+mxw_status mxw_problem_forget_factors(mxw_problem* prob);
 /* Subdomains re-factorised by the last medium change (all of them at
  * creation), and the totals re-factorised and kept over the problem's
  * medium changes.  NULL outputs are skipped. */
@@ -405,6 +408,9 @@ typedef struct {
                                  factors only; 0 where not measured) */
   double multi_tall_ms;       /* time per multi-column local solve with 128-row passes
                                  (FP32 factors only; 0 where not measured) */
+  int32_t lu_launch;          /* LU launch chosen: 1 one workgroup per subdomain, 2 persistent queue */
+  int32_t reserved;
+  double lu_launch_ms[2];     /* time per LU of every A_s with each launch (factorised problems) */
 } mxw_tuning;
 
 /* Autotuner (launch mechanics; not a passage of the paper): times the SpMV
@@ -412,7 +418,8 @@ typedef struct {
  * Boolean partition of unity (ORAS, RAS) and a factorised problem, the
  * multi-column local solve with 4- and 8-wide k slices (for FP32 factors also
  * with 128-row passes); and for FP32 factors (MXW_MIXED, factorised) the LU
- * with 4- and 8-wide k slices (each trial
+ * with 4- and 8-wide k slices and, for every factorised problem, the two
+ * LU launches (each trial
  * re-assembles the local matrices and factorises them again: seconds at a
  * million unknowns; the problem ends factorised with the fastest), all on
  * this problem's own operator and factors; later calls on the problem use
@@ -426,10 +433,14 @@ mxw_status mxw_problem_tune(mxw_problem* prob, int32_t nrhs, void* stream, mxw_t
 /* Sets the tile choices by hand (for instance those a previous
  * mxw_problem_tune call picked): spmv_group in {4, 8, 16, 32}, multi_ku and
  * lu_ku in {4, 8} (lu_ku applies to the next factorisation, FP32 only),
- * multi_rows in {64, 128} (128-row passes take 8-wide slices); 0 leaves a
- * choice unchanged.  MXW_EINVAL for other values. */
+ * multi_rows in {64, 128} (128-row passes take 8-wide slices), lu_launch 1
+ * (one workgroup per subdomain, largest first; the default for FP64 factors)
+ * or 2 (one persistent launch whose resident workgroups take the subdomains,
+ * largest first, from a work counter; the default for FP32 factors); 0
+ * leaves a choice unchanged.  Every choice gives the same
+ * factors bit for bit.  MXW_EINVAL for other values. */
 mxw_status mxw_problem_set_tiles(mxw_problem* prob, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku,
-                                 int32_t multi_rows);
+                                 int32_t multi_rows, int32_t lu_launch);
 
 /* Residual estimates |g_{j+1}| / ||b|| of every Arnoldi step of column col
  * in the last solve on this problem (host array; len receives the count,

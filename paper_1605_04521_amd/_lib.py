@@ -76,7 +76,8 @@ class LayoutInfo(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("spmv_group", C.c_int32), ("multi_ku", C.c_int32), ("spmv_ms", C.c_double * 4),
                 ("multi_ms", C.c_double * 2), ("lu_ku", C.c_int32), ("multi_rows", C.c_int32),
-                ("lu_ms", C.c_double * 2), ("multi_tall_ms", C.c_double)]
+                ("lu_ms", C.c_double * 2), ("multi_tall_ms", C.c_double), ("lu_launch", C.c_int32),
+                ("reserved", C.c_int32), ("lu_launch_ms", C.c_double * 2)]
 
 
 # device-memory provider of a context (see mxw_ctx_create)
@@ -110,6 +111,7 @@ _SIGS = {
     "mxw_ticket_wait": (C.c_int32, [C.c_void_p]),
     "mxw_ticket_destroy": (None, [C.c_void_p]),
     "mxw_problem_device_bytes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "mxw_problem_forget_factors": (C.c_int32, [C.c_void_p]),
     "mxw_problem_factor_stats": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                              C.POINTER(C.c_int64)]),
     "mxw_problem_set_medium": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
@@ -128,7 +130,7 @@ _SIGS = {
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
     "mxw_solve_history": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "mxw_problem_tune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(Tuning)]),
-    "mxw_problem_set_tiles": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "mxw_problem_set_tiles": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "mxw_smatrix": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Source), C.c_int32, C.c_void_p, C.c_void_p,
                                 C.c_void_p]),
     "mxw_solve_recycle": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(SolveOpts), C.c_int32,

@@ -361,10 +361,12 @@ class Problem:
         B.check(B.lib().mxw_problem_tune(self.h, nrhs, _stream(), C.byref(t)))
         return {"spmv_group": t.spmv_group, "multi_ku": t.multi_ku, "spmv_ms": list(t.spmv_ms),
                 "multi_ms": list(t.multi_ms), "lu_ku": t.lu_ku, "lu_ms": list(t.lu_ms),
-                "multi_rows": t.multi_rows, "multi_tall_ms": t.multi_tall_ms}
+                "multi_rows": t.multi_rows, "multi_tall_ms": t.multi_tall_ms, "lu_launch": t.lu_launch,
+                "lu_launch_ms": list(t.lu_launch_ms)}
 
-    def set_tiles(self, spmv_group: int = 0, multi_ku: int = 0, lu_ku: int = 0, multi_rows: int = 0):
-        B.check(B.lib().mxw_problem_set_tiles(self.h, spmv_group, multi_ku, lu_ku, multi_rows))
+    def set_tiles(self, spmv_group: int = 0, multi_ku: int = 0, lu_ku: int = 0, multi_rows: int = 0,
+                  lu_launch: int = 0):
+        B.check(B.lib().mxw_problem_set_tiles(self.h, spmv_group, multi_ku, lu_ku, multi_rows, lu_launch))
 
     def history(self, col: int = 0) -> np.ndarray:
         """Relative residual estimates of every Arnoldi step of the last solve."""
@@ -410,6 +412,10 @@ class Problem:
         B.check(B.lib().mxw_solve_async(self.h, len(sources), src, C.byref(opts), C.c_void_p(st.cuda_stream),
                                         x.data_ptr(), 1, it.ctypes.data, rr.ctypes.data, C.byref(h)))
         return Ticket(self, h, x, it, rr, src)
+
+    def forget_factors(self):
+        """The next set_medium factorises every subdomain again."""
+        B.check(B.lib().mxw_problem_forget_factors(self.h))
 
     def factor_stats(self) -> dict:
         """Subdomains re-factorised by the last medium change; totals over the changes."""

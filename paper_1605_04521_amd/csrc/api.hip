@@ -426,6 +426,8 @@ struct mxw_problem {
   uint64_t op_gen = 0;    // bumped whenever A or M changes (recycled spaces go stale)
   // factor residency per subdomain (assemble_medium)
   int* sub_list = nullptr;             // device: subdomains to re-factorise
+  int* lu_counter = nullptr;           // device: work counter of the persistent LU launch
+  bool lu_persistent = false;          // LU launch: persistent queue (tunable) or one workgroup per subdomain
   std::vector<uint64_t> sub_hash;      // local-data hash each subdomain's factors were made for
   bool hash_valid = false;             // the factors match sub_hash (no failed or deferred factorisation)
   int64_t refactor_last = 0, refactor_total = 0, kept_total = 0, medium_updates = 0;
@@ -551,6 +553,7 @@ uint64_t problem_bytes(const Layout& L, int precision) {
   b += nbytes_of<double2>((size_t)L.nt * nloc * nloc);                           // AT
   b += nbytes_of<double2>(L.cols.size());                                       // CSR values
   b += nbytes_of<int>(L.n_sub);                                                 // subdomain list
+  b += nbytes_of<int>(1);                                                       // LU work counter
   return b;
 }
 
@@ -751,6 +754,9 @@ mxw_status check_problem(const mxw_problem* P) {
 
 // list / count: the subdomains to assemble (device ids, largest first);
 // nullptr = all of them
+// the LU's launch: persistent queue or one workgroup per subdomain
+int* lu_queue(mxw_problem* P) { return P->lu_persistent ? P->lu_counter : nullptr; }
+
 template <typename R>
 mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor, const int* list = nullptr,
                                   int count = -1) {
@@ -770,7 +776,7 @@ mxw_status build_local_and_factor(mxw_problem* P, hipStream_t st, bool factor, c
   if (factor) {
     ScopedKernelTimer tm("lu");
     launch_lu<R>(st, L.n_sub, (R*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (R*)P->lu_scratch, P->info,
-                 P->order, P->lu_ku);
+                 P->order, P->lu_ku, lu_queue(P));
   }
   HIP_CHECK(hipGetLastError());
   return MXW_OK;
@@ -785,11 +791,11 @@ mxw_status factor_impl(mxw_problem* P, hipStream_t st, const int* list = nullptr
   if (P->mixed) {
     ScopedKernelTimer tm("lu");
     launch_lu<float>(st, nf, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (float*)P->lu_scratch,
-                     P->info, ord, P->lu_ku);
+                     P->info, ord, P->lu_ku, lu_queue(P));
   } else {
     ScopedKernelTimer tm("lu");
     launch_lu<double>(st, nf, (double*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff, (double*)P->lu_scratch,
-                      P->info, ord, P->lu_ku);
+                      P->info, ord, P->lu_ku, lu_queue(P));
   }
   HIP_CHECK(hipGetLastError());
   std::vector<int> info(P->L.n_sub);
@@ -1247,6 +1253,8 @@ mxw_status create_problem(const std::shared_ptr<CtxState>& ctx, const std::share
   P->k0 = k0;
   P->mixed = mixed;
   P->multi_rows = mixed ? 128 : 64;   // measured faster in FP32; in FP64 the LDS of 128 rows halves occupancy
+  // persistent LU launch in FP32; in FP64 its loop costs a few spilled registers
+  P->lu_persistent = mixed;
   // views of the shared mirror
   P->xyz = S->xyz;
   P->tets = S->tets;
@@ -1301,8 +1309,9 @@ mxw_status create_problem(const std::shared_ptr<CtxState>& ctx, const std::share
   P->AT = M.alloc<double2>((size_t)L.nt * nloc * nloc);
   P->vals = M.alloc<double2>(L.cols.size());
   P->sub_list = M.alloc<int>(L.n_sub);
+  P->lu_counter = M.alloc<int>(1);
   if (!P->perm || !P->info || !P->F || !P->lu_scratch || !P->AT || !P->vals || !P->eps || !P->imp_beta ||
-      !P->imp_eps || !P->sub_face_coef || !P->sub_list) {
+      !P->imp_eps || !P->sub_face_coef || !P->sub_list || !P->lu_counter) {
     set_error("device allocation failed (factors or element data)");
     return MXW_ENOMEM;
   }
@@ -2411,6 +2420,13 @@ void mxw_ticket_destroy(mxw_ticket* t) {
   delete t;
 }
 
+mxw_status mxw_problem_forget_factors(mxw_problem* P) {
+  TRY(check_problem(P));
+  std::lock_guard<std::mutex> hold(P->run);
+  P->hash_valid = false;
+  return MXW_OK;
+}
+
 mxw_status mxw_problem_factor_stats(const mxw_problem* P, int32_t* refactored_last, int64_t* refactored_total,
                                     int64_t* kept_total) {
   TRY(check_problem(P));
@@ -2431,16 +2447,19 @@ mxw_status mxw_problem_device_bytes(const mxw_problem* P, uint64_t* bytes) {
 }
 
 mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t multi_ku, int32_t lu_ku,
-                                 int32_t multi_rows) {
+                                 int32_t multi_rows, int32_t lu_launch) {
   TRY(check_problem(P));
   const bool g_ok = spmv_group == 0 || spmv_group == 4 || spmv_group == 8 || spmv_group == 16 || spmv_group == 32;
   const bool k_ok = multi_ku == 0 || multi_ku == 4 || multi_ku == 8;
   const bool l_ok = lu_ku == 0 || lu_ku == 4 || lu_ku == 8;
   const bool r_ok = multi_rows == 0 || multi_rows == 64 || multi_rows == 128;
-  if (!g_ok || !k_ok || !l_ok || !r_ok) {
-    set_error("spmv_group must be 0, 4, 8, 16 or 32, multi_ku and lu_ku 0, 4 or 8, multi_rows 0, 64 or 128");
+  const bool q_ok = lu_launch >= 0 && lu_launch <= 2;
+  if (!g_ok || !k_ok || !l_ok || !r_ok || !q_ok) {
+    set_error("spmv_group must be 0, 4, 8, 16 or 32, multi_ku and lu_ku 0, 4 or 8, multi_rows 0, 64 or 128, "
+              "lu_launch 0, 1 or 2");
     return MXW_EINVAL;
   }
+  if (lu_launch) P->lu_persistent = lu_launch == 2;
   if (spmv_group) P->spmv_group = spmv_group;
   if (multi_ku) P->multi_ku = multi_ku;
   if (lu_ku) P->lu_ku = lu_ku;
@@ -2536,7 +2555,7 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
       TRY(build_local_and_factor<float>(P, st, false));
       hipEventRecord(ea, st);
       launch_lu<float>(st, P->L.n_sub, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
-                       (float*)P->lu_scratch, P->info, P->order, P->lu_ku);
+                       (float*)P->lu_scratch, P->info, P->order, P->lu_ku, lu_queue(P));
       hipEventRecord(eb, st);
       hipEventSynchronize(eb);
       float ms = 0.f;
@@ -2554,6 +2573,34 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
     }
   }
   t.lu_ku = P->mixed ? P->lu_ku : 4;
+  if (P->factored) {
+    // the LU's launch: one workgroup per subdomain or the persistent queue
+    // (each trial re-assembles the local matrices first)
+    const bool keep = P->lu_persistent;
+    for (int q = 0; q < 2; ++q) {
+      P->lu_persistent = q == 1;
+      if (P->mixed)
+        TRY(build_local_and_factor<float>(P, st, false));
+      else
+        TRY(build_local_and_factor<double>(P, st, false));
+      hipEventRecord(ea, st);
+      if (P->mixed)
+        launch_lu<float>(st, P->L.n_sub, (float*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
+                         (float*)P->lu_scratch, P->info, P->order, P->lu_ku, lu_queue(P));
+      else
+        launch_lu<double>(st, P->L.n_sub, (double*)P->F, P->foff, P->nsz, P->lds, P->perm, P->poff,
+                          (double*)P->lu_scratch, P->info, P->order, P->lu_ku, lu_queue(P));
+      hipEventRecord(eb, st);
+      hipEventSynchronize(eb);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ea, eb);
+      t.lu_launch_ms[q] = ms;
+    }
+    P->lu_persistent = t.lu_launch_ms[1] <= t.lu_launch_ms[0];
+    (void)keep;
+    ++P->op_gen;   // new factors (the same bits: both launches run the same per-subdomain code)
+  }
+  t.lu_launch = P->lu_persistent ? 2 : 1;
   P->kw.drop_graphs();   // captured steps hold the previous tile kernels
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));

@@ -109,9 +109,11 @@ void launch_rhs_port(hipStream_t st, const PlaneWaveArgs& a, const double c[3], 
                      double aw, double bh, int mode, double2* work, double* fnorm, double* den, double2* b);
 void launch_smatrix_finish(hipStream_t st, int nsol, int np, const double2* num, const double* den, double2* S);
 
+// queue != nullptr: persistent launch (a resident grid takes the n_sub
+// subdomains of order from a counter at *queue, which the launch resets)
 template <typename R>
 void launch_lu(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds, int* perm,
-               const int64_t* poff, R* scratch, int* info, const int* order, int ku);
+               const int64_t* poff, R* scratch, int* info, const int* order, int ku, int* queue = nullptr);
 
 struct LocalSolveArgs {
   int n_sub;

@@ -1,3 +1,4 @@
+#include <algorithm>
 // Batched dense complex LU with partial pivoting of the subdomain matrices A_s
 // (the factorised local solves A_s^{-1} of ORAS, Sec. 4), in FP64 or FP32.
 //
@@ -245,19 +246,19 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
   }
 }
 
+// The factorisation of subdomain s by one workgroup (the body of both
+// launches below).
 template <typename R, int NB, int KU>
-__global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t* __restrict__ foff,
-                                            const int* __restrict__ nsz, const int* __restrict__ lds,
-                                            int* __restrict__ perm, const int64_t* __restrict__ poff,
-                                            R* __restrict__ xscr, int* __restrict__ info,
-                                            const int* __restrict__ order) {
+__device__ __forceinline__ void lu_subdomain(int s, LuSmem<R, NB>& smu, R* __restrict__ F,
+                                             const int64_t* __restrict__ foff, const int* __restrict__ nsz,
+                                             const int* __restrict__ lds, int* __restrict__ perm,
+                                             const int64_t* __restrict__ poff, R* __restrict__ xscr,
+                                             int* __restrict__ info) {
   static_assert(NB == 32, "the sweep tiles assume 32-wide blocks");
   // panel columns updated together per row (fewer in FP64, whose registers
   // are twice as wide)
   constexpr int HC = sizeof(R) == 8 ? 8 : 16;
-  __shared__ LuSmem<R, NB> smu;
   PanelSmem<R, NB>& sm = smu.p;
-  const int s = order ? order[blockIdx.x] : blockIdx.x;
   const int n = nsz[s];
   const int64_t ld = lds[s];
   R* Ar = F + foff[s];
@@ -530,13 +531,71 @@ __global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t*
   if (tid == 0) info[s] = first_zero;
 }
 
+// One workgroup per subdomain (order[blockIdx.x], largest first).
+template <typename R, int NB, int KU>
+__global__ void __launch_bounds__(256, 2) k_lu(R* __restrict__ F, const int64_t* __restrict__ foff,
+                                            const int* __restrict__ nsz, const int* __restrict__ lds,
+                                            int* __restrict__ perm, const int64_t* __restrict__ poff,
+                                            R* __restrict__ xscr, int* __restrict__ info,
+                                            const int* __restrict__ order) {
+  __shared__ LuSmem<R, NB> smu;
+  lu_subdomain<R, NB, KU>(order ? order[blockIdx.x] : blockIdx.x, smu, F, foff, nsz, lds, perm, poff, xscr, info);
+}
+
+// Persistent launch: a grid sized to the resident workgroups takes the
+// subdomains from a queue (order[0..count), largest first) until it is
+// empty; next is a counter that starts at 0.  Every workgroup leaves once it
+// draws an index >= count.
+template <typename R, int NB, int KU>
+__global__ void __launch_bounds__(256, 2) k_lu_queue(R* __restrict__ F, const int64_t* __restrict__ foff,
+                                                  const int* __restrict__ nsz, const int* __restrict__ lds,
+                                                  int* __restrict__ perm, const int64_t* __restrict__ poff,
+                                                  R* __restrict__ xscr, int* __restrict__ info,
+                                                  const int* __restrict__ order, int count, int* __restrict__ next) {
+  __shared__ LuSmem<R, NB> smu;
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(next, 1);
+    __syncthreads();
+    const int q = item;
+    __syncthreads();   // read by all before thread 0 draws again
+    if (q >= count) break;
+    lu_subdomain<R, NB, KU>(order ? order[q] : q, smu, F, foff, nsz, lds, perm, poff, xscr, info);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_counter(int* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
 // ku: k slice width of the block-column update (4 or 8); FP64 always takes 4
 // (8 would spill at two workgroups per CU)
 template <typename R>
 void launch_lu(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* nsz, const int* lds, int* perm,
-               const int64_t* poff, R* scratch, int* info, const int* order, int ku) {
+               const int64_t* poff, R* scratch, int* info, const int* order, int ku, int* queue) {
   if (n_sub <= 0) return;
-  if (sizeof(R) == 8 || ku == 4)
+  const bool k4 = sizeof(R) == 8 || ku == 4;
+  if (queue) {
+    // two workgroups per CU stay resident (launch bounds); never more than
+    // there are subdomains
+    static int cus = 0;
+    if (!cus) {
+      int dev = 0;
+      hipGetDevice(&dev);
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    }
+    const int grid = std::min(n_sub, 2 * cus);
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, queue);
+    if (k4)
+      timed_launch(k_lu_queue<R, kLuNB, 4>, dim3(grid), dim3(256), 0, st, F, foff, nsz, lds, perm, poff, scratch,
+                   info, order, n_sub, queue);
+    else
+      timed_launch(k_lu_queue<R, kLuNB, 8>, dim3(grid), dim3(256), 0, st, F, foff, nsz, lds, perm, poff, scratch,
+                   info, order, n_sub, queue);
+    return;
+  }
+  if (k4)
     timed_launch(k_lu<R, kLuNB, 4>, dim3(n_sub), dim3(256), 0, st, F, foff, nsz, lds, perm, poff, scratch, info,
                  order);
   else
@@ -544,8 +603,8 @@ void launch_lu(hipStream_t st, int n_sub, R* F, const int64_t* foff, const int* 
                  order);
 }
 template void launch_lu<double>(hipStream_t, int, double*, const int64_t*, const int*, const int*, int*,
-                                const int64_t*, double*, int*, const int*, int);
+                                const int64_t*, double*, int*, const int*, int, int*);
 template void launch_lu<float>(hipStream_t, int, float*, const int64_t*, const int*, const int*, int*,
-                               const int64_t*, float*, int*, const int*, int);
+                               const int64_t*, float*, int*, const int*, int, int*);
 
 }  // namespace mxw

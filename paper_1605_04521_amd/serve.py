@@ -258,8 +258,9 @@ class Server:
         self.sched = Scheduler(backend, budget, slots)
         self.poll_s = poll_s
 
-    def run(self, requests, realtime: bool = True):
-        """Returns the wall time of the run."""
+    def run(self, requests, realtime: bool = True, deadline: float = None):
+        """Returns the wall time of the run.  deadline (seconds): requests not
+        started by then are left unserved (error set); running ones finish."""
         t0 = time.perf_counter()
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         if not realtime:
@@ -269,6 +270,13 @@ class Server:
         i = 0
         while True:
             now = time.perf_counter() - t0
+            if deadline is not None and now > deadline:
+                for r in pending[i:]:
+                    r.error = "arrived after the end of the run"
+                for _, _, r in self.sched.waiting:
+                    r.error = "not started before the end of the run"
+                i = len(pending)
+                self.sched.waiting = []
             while i < len(pending) and pending[i].arrival <= now:
                 self.sched.submit(pending[i])
                 i += 1

@@ -8,6 +8,7 @@ context, which counts the bytes in use and their peak; the peak over
 create + solve must equal the footprint up to the plane-wave face-integral
 buffer that dipole sources do not need.
 """
+import gc
 import sys
 import threading
 
@@ -61,7 +62,8 @@ def test_footprint_equals_measured_peak(precision, krylov, nrhs, variant):
     held = torch.cuda.memory_allocated() - alloc0
     assert u["in_use"] <= held <= 1.05 * u["in_use"]
     P.close()
-    del lay
+    del P, lay          # the layout's device copy goes with the last of them
+    gc.collect()
     torch.cuda.synchronize()
     assert ctx.usage()["in_use"] == 0 and ctx.usage()["live"] == 0
     ctx.close()
@@ -80,22 +82,25 @@ def test_budget_rejects_before_allocating():
         Problem.from_layout(lay, precision=B.MXW_MIXED, ctx=small)
     assert e.value.status == B.MXW_ENOMEM
     assert small.usage()["in_use"] == 0
-    # the operator fits, the block workspace of 4 sources does not: the solve
-    # fails with MXW_ENOMEM and the problem stays usable with fewer sources
-    mid = Context(budget=need - 1)
+    # the operator and a pseudo-block solve of the 4 sources fit, the block
+    # workspace does not: the block solve fails with MXW_ENOMEM and the
+    # problem stays usable
+    mid = Context(budget=lay.footprint(B.MXW_MIXED, 4))
+    assert lay.footprint(B.MXW_MIXED, 4) < need
     P = Problem.from_layout(lay, precision=B.MXW_MIXED, ctx=mid)
     with pytest.raises(B.MxwError) as e:
         P.solve_host(prob.sources, krylov=B.MXW_KRYLOV_BLOCK)
     assert e.value.status == B.MXW_ENOMEM
-    assert mid.usage()["peak"] <= need - 1
-    E, it, rr, st = P.solve_host(prob.sources[:1])
-    assert rr[0] <= 1e-8
+    assert mid.usage()["peak"] <= lay.footprint(B.MXW_MIXED, 4)
+    E, it, rr, st = P.solve_host(prob.sources)
+    assert np.all(rr <= 1e-8)
     # a context with memory still held cannot be destroyed
     with pytest.raises(B.MxwError) as e:
         mid.close()
     assert e.value.status == B.MXW_EBUSY
     P.close()
-    del lay
+    del P, lay
+    gc.collect()
     mid.close()
 
 

@@ -486,6 +486,8 @@ def test_tile_choices_agree(precision):
         assert t["multi_tall_ms"] > 0 and t["multi_rows"] in (64, 128)
         if t["multi_rows"] == 128:
             assert t["multi_tall_ms"] <= min(t["multi_ms"])
+    assert t["lu_launch"] in (1, 2) and min(t["lu_launch_ms"]) > 0
+    assert t["lu_launch_ms"][t["lu_launch"] - 1] == min(t["lu_launch_ms"])
     # both k slice widths of the LU (FP32 factors; FP64 always takes 4)
     Q = Problem.from_problem(prob, precision=precision, defer_factor=True)
     Q.set_tiles(lu_ku=4)
@@ -493,6 +495,15 @@ def test_tile_choices_agree(precision):
     Zq = to_np(Q.apply_prec(Vt))
     for c in range(33):
         assert np.linalg.norm(Zq[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
+    # both LU launches (one workgroup per subdomain, persistent queue) give the
+    # same factors bit for bit
+    Zl = {}
+    for launch in (1, 2):
+        Q = Problem.from_problem(prob, precision=precision, defer_factor=True)
+        Q.set_tiles(lu_launch=launch)
+        Q.factor()
+        Zl[launch] = to_np(Q.apply_prec(Vt))
+    assert np.array_equal(Zl[1], Zl[2])
     with pytest.raises(B.MxwError):
         P.set_tiles(spmv_group=12)
     with pytest.raises(B.MxwError):
@@ -500,29 +511,33 @@ def test_tile_choices_agree(precision):
     with pytest.raises(B.MxwError):
         P.set_tiles(multi_rows=96)
     with pytest.raises(B.MxwError):
+        P.set_tiles(lu_launch=3)
+    with pytest.raises(B.MxwError):
         P.tune(nrhs=0)
 
 
 def test_close_releases_device_memory_with_timing_on():
     """A closed problem returns its device memory also while kernel timing is
-    on (recorded timing events must not keep its buffers alive)."""
-    from paper_1605_04521_amd.api import reset_timing, timing
+    on (recorded timing events must not keep its buffers alive): its context
+    holds nothing afterwards and PyTorch's allocator is back where it was."""
+    from paper_1605_04521_amd.api import Context, reset_timing, timing
     prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2, n_sources=4)
     say("[gpu] close with timing on")
     torch.cuda.synchronize()
-    free0 = torch.cuda.mem_get_info()[0]
-    P = Problem.from_problem(prob, precision=B.MXW_MIXED)
+    base = torch.cuda.memory_allocated()
+    ctx = Context()
+    P = Problem.from_problem(prob, precision=B.MXW_MIXED, ctx=ctx)
     timing(True)
     reset_timing()
     try:
         P.solve(prob.sources, krylov=B.MXW_KRYLOV_BLOCK)
         torch.cuda.synchronize()
-        used = free0 - torch.cuda.mem_get_info()[0]
+        used = ctx.usage()["in_use"]
         P.close()
         torch.cuda.synchronize()
-        torch.cuda.empty_cache()
-        left = free0 - torch.cuda.mem_get_info()[0]
+        left = ctx.usage()["in_use"]
     finally:
         timing(False)
     say(f"   in use with the problem {used / 1e6:.0f} MB, after close {left / 1e6:.0f} MB")
-    assert used > 100e6 and left < 0.1 * used
+    assert used > 100e6 and left == 0
+    assert torch.cuda.memory_allocated() <= base
