@@ -349,6 +349,13 @@ struct BlockWork {
   int* info = nullptr;   // [0] rank loss, [1] second Gram-Schmidt pass needed
   int64_t reorth = 0;    // second passes in the last solve
   int64_t deflated = 0;  // block steps with a floor pivot in the Cholesky QR
+  std::vector<hipGraphExec_t> graphs;   // captured block Arnoldi step per index j
+  void drop_graphs() {
+    for (auto& e : graphs)
+      if (e) hipGraphExecDestroy(e);
+    graphs.clear();
+  }
+  ~BlockWork() { drop_graphs(); }
 };
 
 // Krylov recycling (GCRO-DR) state, kept across solves: the basis array
@@ -626,6 +633,7 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
   KrylovWork& k = P->kw;
   if (k.nrhs >= nrhs && k.m == m && k.ndof == P->L.ndof && k.V) return MXW_OK;
   k.drop_graphs();
+  P->bw.drop_graphs();   // block steps captured with the old bases
   k.mem.reset();
   if (k.host) {
     hipHostFree(k.host);
@@ -1336,6 +1344,7 @@ mxw_status create_problem(const std::shared_ptr<CtxState>& ctx, const std::share
 mxw_status ensure_block_ws(BlockWork& b, int64_t n, int p, int m, bool with_xi = false) {
   const bool want_xi = with_xi && p >= kIlMinCols;
   if (b.p == p && b.m == m && b.ndof == n && b.H1 && (b.Xi != nullptr) == want_xi) return MXW_OK;
+  b.drop_graphs();
   b.mem.reset();
   b.p = p;
   b.m = m;
@@ -1374,25 +1383,26 @@ mxw_status ensure_block(mxw_problem* P, int p, int m) { return ensure_block_ws(P
 // out (Q x p, column-major) = A^H W, A: Q vectors of length n, W: p vectors,
 // as split-K partial products summed in a fixed order
 mxw_status gram(BlockWork& b, int64_t n, hipStream_t st, const double2* A, int Q, const double2* W, int p,
-                double2* out) {
+                double2* out, const int* cond = nullptr) {
   // about 2048 workgroups, within the partial-product buffer (sized for
   // kMaxGramParts parts of the largest Q)
   const int qtiles = (Q + 63) / 64;
   const int cap = (int)std::min<int64_t>(4096, (int64_t)kMaxGramParts * (b.m + 1) * b.p / Q);
   const int want = std::max(1, std::min(cap, 2048 / qtiles));
-  launch_bgram(st, A, Q, W, p, n, want, b.part);
-  launch_gram_reduce(st, (int64_t)Q * p, bgram_parts(n, want), b.part, out);
+  launch_bgram(st, A, Q, W, p, n, want, b.part, cond);
+  launch_gram_reduce(st, (int64_t)Q * p, bgram_parts(n, want), b.part, out, cond);
   return MXW_OK;
 }
 
-mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const double2* W, int p, double2* out) {
-  return gram(P->bw, P->L.ndof, st, A, Q, W, p, out);
+mxw_status gram(mxw_problem* P, hipStream_t st, const double2* A, int Q, const double2* W, int p, double2* out,
+                const int* cond = nullptr) {
+  return gram(P->bw, P->L.ndof, st, A, Q, W, p, out, cond);
 }
 
 // C (n x p) = alpha A M + beta C; A: K vectors of length n, M: K x p (ld ldm)
 mxw_status tall_gemm(mxw_problem* P, hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p,
-                     double alpha, double beta, double2* C) {
-  launch_bupdate(st, A, K, M, ldm, p, P->L.ndof, alpha, beta, C, C);
+                     double alpha, double beta, double2* C, const int* cond = nullptr) {
+  launch_bupdate(st, A, K, M, ldm, p, P->L.ndof, alpha, beta, C, C, cond);
   return MXW_OK;
 }
 
@@ -1460,30 +1470,62 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
       double2* Vj = k.V + (int64_t)j * p * n;
       double2* Zj = k.Z + (int64_t)j * p * n;
       const int Q = (j + 1) * p;
-      apply_prec_dev(P, st, Vj, n, Zj, n, p, nullptr, k.YS, k.xbuf);
-      block_spmv(P, st, Zj, k.W, nullptr, p);
-      // block classical Gram-Schmidt; a second pass where a column lost more
-      // than 1 - 1/sqrt(2) of its norm in the first
-      TRY(gram(P, st, k.W, p, k.W, p, b.G0));
-      TRY(gram(P, st, k.V, Q, k.W, p, b.H1));
-      TRY(tall_gemm(P, st, k.V, Q, b.H1, Q, p, -1.0, 1.0, k.W));
-      TRY(gram(P, st, k.W, p, k.W, p, b.G));
-      launch_reorth_check(st, p, b.G0, b.G, b.info + 1);
-      HIP_CHECK(hipMemcpyAsync(hbuf + p + 1, b.info + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipStreamSynchronize(st));
-      int again = 0;
-      std::memcpy(&again, hbuf + p + 1, sizeof(int));
-      if (again) {
-        ++b.reorth;
-        TRY(gram(P, st, k.V, Q, k.W, p, b.H2));
-        TRY(tall_gemm(P, st, k.V, Q, b.H2, Q, p, -1.0, 1.0, k.W));
+      // one block Arnoldi step, every decision on the device: block
+      // classical Gram-Schmidt, a second pass only where a column lost more
+      // than 1 - 1/sqrt(2) of its norm in the first (flag b.info[1], read by
+      // the kernels of that pass), Cholesky QR twice, the least-squares update
+      auto step = [&](hipStream_t s) -> mxw_status {
+        apply_prec_dev(P, s, Vj, n, Zj, n, p, nullptr, k.YS, k.xbuf);
+        block_spmv(P, s, Zj, k.W, nullptr, p);
+        TRY(gram(P, s, k.W, p, k.W, p, b.G0));
+        TRY(gram(P, s, k.V, Q, k.W, p, b.H1));
+        TRY(tall_gemm(P, s, k.V, Q, b.H1, Q, p, -1.0, 1.0, k.W));
+        TRY(gram(P, s, k.W, p, k.W, p, b.G));
+        launch_reorth_check(s, p, b.G0, b.G, b.info + 1);
+        TRY(gram(P, s, k.V, Q, k.W, p, b.H2, b.info + 1));
+        TRY(tall_gemm(P, s, k.V, Q, b.H2, Q, p, -1.0, 1.0, k.W, b.info + 1));
+        TRY(gram(P, s, k.W, p, k.W, p, b.G, b.info + 1));   // the Gram matrix after the second pass
+        // V_{j+1} S = W
+        TRY(cholqr2(P, P->bw, s, k.W, k.Rv, k.V + (int64_t)(j + 1) * p * n, p, true));
+        launch_bls_step(s, j, p, m, b.H1, b.H2, b.S, b.Hc, b.T, b.Rls, b.E, b.est, b.info + 1);
+        return MXW_OK;
+      };
+      if (opts->use_graph) {
+        // the step of index j captured once per workspace and replayed (fixed
+        // device addresses, j and Q as constants; the changing state lives in
+        // device memory); capture on a private stream
+        if ((int)b.graphs.size() < m) b.graphs.resize(m, nullptr);
+        if (!b.graphs[j]) {
+          if (!k.cap) HIP_CHECK(hipStreamCreateWithFlags(&k.cap, hipStreamNonBlocking));
+          hipGraph_t g = nullptr;
+          g_capturing = true;
+          hipError_t ce = hipStreamBeginCapture(k.cap, hipStreamCaptureModeThreadLocal);
+          mxw_status ss = MXW_OK;
+          if (ce == hipSuccess) {
+            ss = step(k.cap);
+            ce = hipStreamEndCapture(k.cap, &g);
+          }
+          g_capturing = false;
+          if (ce != hipSuccess) return dev_fail("graph capture", ce);
+          if (ss != MXW_OK) {
+            hipGraphDestroy(g);
+            return ss;
+          }
+          const hipError_t ie = hipGraphInstantiate(&b.graphs[j], g, nullptr, nullptr, 0);
+          hipGraphDestroy(g);
+          if (ie != hipSuccess) {
+            b.graphs[j] = nullptr;
+            return dev_fail("hipGraphInstantiate", ie);
+          }
+        }
+        HIP_CHECK(hipGraphLaunch(b.graphs[j], st));
+      } else {
+        TRY(step(st));
       }
-      // V_{j+1} S = W
-      TRY(cholqr2(P, P->bw, st, k.W, k.Rv, k.V + (int64_t)(j + 1) * p * n, p, !again));
-      launch_bls_step(st, j, p, m, b.H1, again ? b.H2 : nullptr, b.S, b.Hc, b.T, b.Rls, b.E, b.est);
       HIP_CHECK(hipGetLastError());
+      // the step's one readback: residual estimates and the two flags
       HIP_CHECK(hipMemcpyAsync(hbuf, b.est, sizeof(double) * p, hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipMemcpyAsync(hbuf + p, b.info, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipMemcpyAsync(hbuf + p, b.info, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
       HIP_CHECK(hipStreamSynchronize(st));
       ++steps;
       jd = j + 1;
@@ -1492,9 +1534,10 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
         k.history[c].push_back(hbuf[c] / bnorm[c]);
         if (!(hbuf[c] <= opts->tol * bnorm[c])) all = false;
       }
-      int info = 0;
-      std::memcpy(&info, hbuf + p, sizeof(int));
-      if (info) {
+      int info[2] = {0, 0};
+      std::memcpy(info, hbuf + p, 2 * sizeof(int));
+      if (info[1]) ++b.reorth;
+      if (info[0]) {
         // the new block is numerically rank deficient: the Cholesky QR kept a
         // floor pivot, the direction carries a negligible weight in the least
         // squares and the true residual at the cycle end decides
@@ -2466,6 +2509,7 @@ mxw_status mxw_problem_set_tiles(mxw_problem* P, int32_t spmv_group, int32_t mul
   if (multi_rows) P->multi_rows = multi_rows;
   if (P->multi_rows == 128) P->multi_ku = 8;   // 128-row passes take 8-wide slices
   P->kw.drop_graphs();   // captured steps hold the previous tile kernels
+  P->bw.drop_graphs();
   return MXW_OK;
 }
 
@@ -2602,6 +2646,7 @@ mxw_status mxw_problem_tune(mxw_problem* P, int32_t nrhs, void* stream, mxw_tuni
   }
   t.lu_launch = P->lu_persistent ? 2 : 1;
   P->kw.drop_graphs();   // captured steps hold the previous tile kernels
+  P->bw.drop_graphs();
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));
   if (out) *out = t;

@@ -25,7 +25,8 @@ constexpr int kMaxBlockP = 32;
 // 16 groups of 16 threads sum interleaved parts, and the 16 group sums are
 // added in LDS in a fixed order (deterministic for a given part count).
 __global__ void __launch_bounds__(256) k_gram_reduce(int64_t len, int nparts, const double2* __restrict__ part,
-                                                     double2* __restrict__ H) {
+                                                     double2* __restrict__ H, const int* __restrict__ cond) {
+  if (cond && !*cond) return;   // a step's optional work, decided on the device
   __shared__ double2 acc[16][17];
   const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int64_t idx = (int64_t)blockIdx.x * 16 + o;
@@ -48,9 +49,9 @@ __global__ void __launch_bounds__(256) k_gram_reduce(int64_t len, int nparts, co
   }
 }
 
-void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H) {
+void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H, const int* cond) {
   if (len == 0) return;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, H);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((len + 15) / 16)), dim3(256), 0, st, len, nparts, part, H, cond);
 }
 
 // ---------------------------------------------------------------------------
@@ -65,7 +66,9 @@ constexpr int kGramChunkStep = 32;   // n entries staged per LDS step
 // waves of a workgroup take 16 rows q each; the W and V strips of every
 // 32-entry step are staged in LDS with coalesced loads.
 __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
-                                               int p, int64_t n, int64_t chunk, double2* __restrict__ part) {
+                                               int p, int64_t n, int64_t chunk, double2* __restrict__ part,
+                                               const int* __restrict__ cond) {
+  if (cond && !*cond) return;   // a step's optional work, decided on the device
   typedef Mfma<double>::acc_t acc_t;
   constexpr int S = kGramChunkStep;
   __shared__ double2 Vs[64][S + 1];
@@ -132,10 +135,10 @@ __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, in
 }
 
 void launch_bgram(hipStream_t st, const double2* V, int Q, const double2* W, int p, int64_t n, int nchunks,
-                  double2* part) {
+                  double2* part, const int* cond) {
   const int64_t chunk = ((n + nchunks - 1) / nchunks + kGramChunkStep - 1) / kGramChunkStep * kGramChunkStep;
   const int used = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(k_bgram, dim3((Q + 63) / 64, used), dim3(256), 0, st, V, Q, W, p, n, chunk, part);
+  hipLaunchKernelGGL(k_bgram, dim3((Q + 63) / 64, used), dim3(256), 0, st, V, Q, W, p, n, chunk, part, cond);
 }
 
 int bgram_parts(int64_t n, int nchunks) {
@@ -149,7 +152,8 @@ int bgram_parts(int64_t n, int nchunks) {
 // out are coalesced); a workgroup covers 128 entries i.  out may be C.
 __global__ void __launch_bounds__(256) k_bupdate(const double2* __restrict__ A, int K, const double2* __restrict__ M,
                                                  int ldm, int p, int64_t n, double alpha, double beta,
-                                                 const double2* C, double2* out) {
+                                                 const double2* C, double2* out, const int* __restrict__ cond) {
+  if (cond && !*cond) return;   // a step's optional work, decided on the device
   typedef Mfma<double>::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int64_t ibase = (int64_t)blockIdx.x * 128 + wave * 32;
@@ -209,9 +213,9 @@ __global__ void __launch_bounds__(256) k_bupdate(const double2* __restrict__ A, 
 }
 
 void launch_bupdate(hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p, int64_t n,
-                    double alpha, double beta, const double2* C, double2* out) {
+                    double alpha, double beta, const double2* C, double2* out, const int* cond) {
   hipLaunchKernelGGL(k_bupdate, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, A, K, M, ldm, p, n, alpha,
-                     beta, C, out);
+                     beta, C, out, cond);
 }
 
 // Cholesky G = R^H R (R upper, p x p) and R^{-1}; optionally S = R Rprev.
@@ -363,10 +367,13 @@ void launch_set_e(hipStream_t st, int p, int ldE, const double2* S0, double2* E)
 //      -e^{i arg x_0} |x|; Q_j^H = H_{p-1} ... H_0 stored in T_j;
 //   4. E window <- Q_j^H E window; R column block stored; est = row norms.
 __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const double2* __restrict__ H1,
-                                                  const double2* __restrict__ H2, const double2* __restrict__ S,
+                                                  const double2* __restrict__ H2in, const double2* __restrict__ S,
                                                   double2* __restrict__ Hc, double2* __restrict__ T,
                                                   double2* __restrict__ Rls, double2* __restrict__ E,
-                                                  double* __restrict__ est) {
+                                                  double* __restrict__ est, const int* __restrict__ h2_used) {
+  // H2 (the second Gram-Schmidt pass's coefficients) counts only when the
+  // step took that pass (a flag set on the device)
+  const double2* __restrict__ H2 = (H2in && (!h2_used || *h2_used)) ? H2in : nullptr;
   __shared__ double2 A[2 * kMaxBlockP][kMaxBlockP + 1];
   __shared__ double2 B[2 * kMaxBlockP][kMaxBlockP + 1];
   __shared__ double2 Qt[2 * kMaxBlockP][2 * kMaxBlockP + 1];
@@ -537,8 +544,8 @@ __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const dou
 }
 
 void launch_bls_step(hipStream_t st, int j, int p, int m, const double2* H1, const double2* H2, const double2* S,
-                     double2* Hc, double2* T, double2* Rls, double2* E, double* est) {
-  hipLaunchKernelGGL(k_bls_step, dim3(1), dim3(256), 0, st, j, p, m, H1, H2, S, Hc, T, Rls, E, est);
+                     double2* Hc, double2* T, double2* Rls, double2* E, double* est, const int* h2_used) {
+  hipLaunchKernelGGL(k_bls_step, dim3(1), dim3(256), 0, st, j, p, m, H1, H2, S, Hc, T, Rls, E, est, h2_used);
 }
 
 // Y = R^{-1} E[0:jp, :] (R = Rls[0:jp, 0:jp], upper); Y has leading dimension m p.

@@ -143,17 +143,20 @@ void launch_gather_all(hipStream_t st, int64_t ndof, const int64_t* ptr, const i
 
 // block GMRES: split-K Gram reduction, Cholesky + inverse of a p x p Gram
 // matrix, block Hessenberg least-squares step and back substitution
-void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H);
+// cond (device flag, optional): the launch does its work only when *cond != 0
+void launch_gram_reduce(hipStream_t st, int64_t len, int nparts, const double2* part, double2* H,
+                        const int* cond = nullptr);
 void launch_bgram(hipStream_t st, const double2* V, int Q, const double2* W, int p, int64_t n, int nchunks,
-                  double2* part);
+                  double2* part, const int* cond = nullptr);
 int bgram_parts(int64_t n, int nchunks);
 void launch_bupdate(hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p, int64_t n,
-                    double alpha, double beta, const double2* C, double2* out);
+                    double alpha, double beta, const double2* C, double2* out, const int* cond = nullptr);
 void launch_chol(hipStream_t st, int p, const double2* G, double2* R, double2* Rinv, const double2* Rprev,
                  double2* S, int* info);
 void launch_set_e(hipStream_t st, int p, int ldE, const double2* S0, double2* E);
+// h2_used (device flag, optional): H2 counts only when *h2_used != 0
 void launch_bls_step(hipStream_t st, int j, int p, int m, const double2* H1, const double2* H2, const double2* S,
-                     double2* Hc, double2* T, double2* Rls, double2* E, double* est);
+                     double2* Hc, double2* T, double2* Rls, double2* E, double* est, const int* h2_used = nullptr);
 void launch_bls_solve(hipStream_t st, int jp, int p, int m, const double2* Rls, const double2* E, double2* Y);
 void launch_reorth_check(hipStream_t st, int p, const double2* G0, const double2* G1, int* flag);
 int max_block_p();
