@@ -48,16 +48,26 @@ def test_rhs_noalloc_matches_rhs():
 
 
 def test_rhs_noalloc_allocates_nothing():
+    """No allocation through the problem's context (whose allocator is
+    PyTorch's) and none behind PyTorch's back, over repeated calls."""
+    from paper_1605_04521_amd.api import Context
     prob = gen.cube_planewave_problem(n=6, degree=2, box=3, n_sources=2)
-    P = Problem.from_problem(prob, defer_factor=True)
+    ctx = Context()
+    P = Problem.from_problem(prob, defer_factor=True, ctx=ctx)
     out = torch.empty((2, P.ndof), dtype=torch.complex128, device="cuda")
     P.rhs_noalloc(prob.sources, out=out)      # first call on the device looks the buffer up
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
+    u0 = ctx.usage(reset_peak=True)
     for _ in range(5):
         P.rhs_noalloc(prob.sources, out=out)
     torch.cuda.synchronize()
+    u1 = ctx.usage()
     assert torch.cuda.mem_get_info()[0] == free0
+    assert u1["peak"] == u0["in_use"] == u1["in_use"] and u1["live"] == u0["live"]
+    # the allocating entry point, for contrast, takes its face buffer through the context
+    P.rhs(prob.sources)
+    assert ctx.usage()["peak"] > u1["in_use"]
 
 
 def slab_problem(n):
