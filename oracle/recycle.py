@@ -218,3 +218,143 @@ def _deflate(space: RecycleSpace, kk, jd, V, Z, H, Bm):
         U = V[:jd].T @ PR
         Ubar = Z[:jd].T @ PR
     space.C, space.U, space.Ubar = C, U, Ubar
+
+
+# ---------------------------------------------------------------------------
+# Block GCRO-DR: the same recycling for a block of right-hand sides
+# ---------------------------------------------------------------------------
+# Sec. 6 names the combination of block and recycling strategies (a "Block
+# GCRO-DR" method) for the many transmitting antennas of the imaging loop.
+# This is GCRO-DR above with a block Krylov space (the block FGMRES oracle of
+# krylov.py) in place of the single-vector one:
+# * a cycle removes from the block residual its part in range(C), then runs
+#   block Arnoldi for (I - C C^H) Ap from the QR of that residual,
+#   Ap Z_j = C B_j + [V_0 .. V_{j+1}] Hbar_j, each block orthogonalised against
+#   C and then the previous blocks (block modified Gram-Schmidt) and
+#   factorised by Householder QR;
+# * the least squares over range([U, V]) splits as in GCRO-DR: the V part is
+#   the block GMRES problem min ||E1 S0 - Hbar Y||_F, the U part is -B Y;
+# * the deflated restart takes the k harmonic Ritz vectors of Ap with respect
+#   to range([U, V_j]) of smallest harmonic Ritz value, with Gbar =
+#   [[D, B], [0, Hbar]] of size (kk + (j+1) p) x (kk + j p);
+# * the cycle length `restart` counts vectors: (restart - kk) // p block steps
+#   (restart // p without a recycled space), at least one;
+# * iterations count block steps; the space is carried to a new operator as
+#   in GCRO-DR.
+# With p = 1 this is GCRO-DR (the tests check it).
+
+def _householder_qr(W):
+    from .krylov import householder_qr
+    return householder_qr(W)
+
+
+def block_gcrodr(matvec_block, precond_block, B, space: RecycleSpace, fresh_operator=True, tol=1e-8, restart=50,
+                 max_iters=5000, history=None):
+    """Solve A X = B (columns of B), using and then replacing the recycled space.
+
+    Returns (X, block steps, true relative residual per column, converged)."""
+    B = np.asarray(B, dtype=np.complex128)
+    n, p = B.shape
+    m, k = int(restart), space.k
+    if k >= m:
+        raise ValueError("the recycled dimension must be below the cycle length")
+    X = np.zeros_like(B)
+    bn = np.linalg.norm(B, axis=0)
+    if np.any(bn == 0.0):
+        raise ValueError("block GCRO-DR needs non-zero right-hand sides")
+    if space.dim and fresh_operator:
+        _refresh(space, lambda v: matvec_block(v[:, None])[:, 0], lambda v: precond_block(v[:, None])[:, 0])
+    R = B.copy()
+    steps = 0
+    while True:
+        kk = space.dim
+        if kk:
+            T = space.C.conj().T @ R
+            X = X + space.Ubar @ T
+            R = R - space.C @ T
+        if np.all(np.linalg.norm(R, axis=0) <= tol * bn):
+            rt = np.linalg.norm(B - matvec_block(X), axis=0) / bn
+            if np.all(rt <= tol):
+                return X, steps, rt, True
+        nb = max(1, (m - kk) // p)
+        V1, S0 = _householder_qr(R)
+        Vs, Zs = [V1], []
+        H = np.zeros(((nb + 1) * p, nb * p), dtype=np.complex128)
+        Bm = np.zeros((kk, nb * p), dtype=np.complex128)
+        E = np.zeros(((nb + 1) * p, p), dtype=np.complex128)
+        E[:p, :] = S0
+        jd = 0
+        for j in range(nb):
+            Zj = precond_block(Vs[j])
+            Zs.append(Zj)
+            W = matvec_block(Zj)
+            if kk:                                   # against C
+                Bj = space.C.conj().T @ W
+                Bm[:, j * p:(j + 1) * p] = Bj
+                W = W - space.C @ Bj
+            for i in range(j + 1):                   # against the previous blocks
+                Hij = Vs[i].conj().T @ W
+                H[i * p:(i + 1) * p, j * p:(j + 1) * p] = Hij
+                W = W - Vs[i] @ Hij
+            Q, Rr = _householder_qr(W)
+            H[(j + 1) * p:(j + 2) * p, j * p:(j + 1) * p] = Rr
+            Vs.append(Q)
+            steps += 1
+            jd = j + 1
+            Hk = H[:(jd + 1) * p, :jd * p]
+            Qh, _ = np.linalg.qr(Hk, mode="complete")
+            G = Qh.conj().T @ E[:(jd + 1) * p, :]
+            est = np.linalg.norm(G[jd * p:, :], axis=0)
+            if history is not None:
+                history.append(est / bn)
+            if np.all(est <= tol * bn) or steps >= max_iters:
+                break
+        Hk = H[:(jd + 1) * p, :jd * p]
+        Qh, Rh = np.linalg.qr(Hk, mode="reduced")
+        Y = np.linalg.solve(Rh, Qh.conj().T @ E[:(jd + 1) * p, :])
+        Zcat = np.concatenate(Zs[:jd], axis=1)
+        X = X + Zcat @ Y
+        if kk:
+            X = X - space.Ubar @ (Bm[:, :jd * p] @ Y)
+        Vcat = np.concatenate(Vs[:jd + 1], axis=1)
+        _deflate_block(space, kk, jd * p, Vcat, Zcat, Hk, Bm[:, :jd * p])
+        R = B - matvec_block(X)
+        rt = np.linalg.norm(R, axis=0) / bn
+        if np.all(rt <= tol):
+            return X, steps, rt, True
+        if steps >= max_iters or not np.all(np.isfinite(rt)):
+            return X, steps, rt, False
+
+
+def _deflate_block(space: RecycleSpace, kk, q, Vcat, Zcat, Hbar, Bm):
+    """The deflated restart of a block cycle: q = j p Krylov vectors, Vcat
+    [n, q + p], Zcat [n, q], Hbar [(q + p), q], Bm [kk, q]."""
+    p = Vcat.shape[1] - q
+    s = kk + q
+    knew = min(space.k, s)
+    if knew == 0:
+        return
+    G = np.zeros((s + p, s), dtype=np.complex128)
+    WV = np.zeros((s + p, s), dtype=np.complex128)
+    if kk:
+        d = 1.0 / np.linalg.norm(space.U, axis=0)
+        G[:kk, :kk] = np.diag(d)
+        G[:kk, kk:] = Bm
+        UD = space.U * d
+        WV[:kk, :kk] = space.C.conj().T @ UD
+        WV[kk:, :kk] = Vcat.conj().T @ UD
+    G[kk:, kk:] = Hbar
+    WV[kk:kk + q, kk:] = np.eye(q)
+    P, _ = harmonic_ritz(G, WV, knew)
+    Qg, Rg = np.linalg.qr(G @ P)
+    PR = P @ np.linalg.inv(Rg)
+    if kk:
+        d = 1.0 / np.linalg.norm(space.U, axis=0)
+        C = np.concatenate([space.C, Vcat], axis=1) @ Qg
+        U = (space.U * d) @ PR[:kk] + Vcat[:, :q] @ PR[kk:]
+        Ubar = (space.Ubar * d) @ PR[:kk] + Zcat @ PR[kk:]
+    else:
+        C = Vcat @ Qg
+        U = Vcat[:, :q] @ PR
+        Ubar = Zcat @ PR
+    space.C, space.U, space.Ubar = C, U, Ubar
