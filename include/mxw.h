@@ -373,12 +373,24 @@ mxw_status mxw_smatrix(mxw_problem* prob, int32_t nports, const mxw_source* port
  *    exists yet), updates x, and replaces the space by the k harmonic Ritz
  *    vectors of smallest harmonic Ritz value of the cycle's search space.
  * opts->restart = vectors per cycle (k < restart <= 64), 1 <= k <= 32,
- * opts->tol, opts->max_iters as for mxw_solve; opts->krylov and use_graph
- * are ignored.  iters_out counts Arnoldi steps.  A different k or restart
- * than the previous call drops the space.  Device memory held by the
- * problem: (2 restart + 5 k + 3) ndof complex128 and small matrices.
- * MXW_ENOTCONV / MXW_EBREAKDOWN as for mxw_solve; MXW_EINVAL for bad
- * options or an unfactorised problem. */
+ * opts->tol, opts->max_iters as for mxw_solve; use_graph is ignored.
+ * iters_out counts Arnoldi steps.
+ * Block GCRO-DR (Sec. 6 combines the block and the recycling strategies):
+ * with opts->krylov = MXW_KRYLOV_BLOCK and 2 <= nrhs <= 16 the nrhs columns
+ * are solved together in one block space: every cycle removes the block
+ * residual's part in range(C), runs (restart - dim) / nrhs block Arnoldi
+ * steps of (I - C C^H) A M^{-1} (block CGS2 against C and the previous
+ * blocks, Cholesky QR of each new block, block least squares), and the new
+ * space is the k harmonic Ritz vectors of the cycle's search space, whose
+ * projected matrix has nrhs rows below the Krylov part (restart + nrhs <=
+ * 65).  iters_out then counts block steps (the same for every column).
+ * Other krylov values solve the columns one after another as above.
+ * A different k or restart than the previous call drops the space; a
+ * different block width keeps it.  Device memory held by the problem:
+ * (2 restart + 5 k + 3 p) ndof complex128 (p the widest block used so far,
+ * 1 without blocks) and small matrices.  MXW_ENOTCONV /
+ * MXW_EBREAKDOWN as for mxw_solve; MXW_EINVAL for bad options, a zero
+ * right-hand side in a block, or an unfactorised problem. */
 mxw_status mxw_solve_recycle(mxw_problem* prob, int32_t nrhs, const double* b_dev,
                              const mxw_solve_opts* opts, int32_t k, void* stream, double* x_dev,
                              int32_t* iters_out, double* relres_out);

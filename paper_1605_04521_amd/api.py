@@ -319,17 +319,21 @@ class Problem:
         B.check(B.lib().mxw_smatrix(self.h, len(ports), src, X.shape[0], X.data_ptr(), _stream(), S.data_ptr()))
         return S
 
-    def solve_recycle(self, b, k: int = 10, tol=1e-8, restart=50, max_iters=5000, allow_notconv=False):
+    def solve_recycle(self, b, k: int = 10, tol=1e-8, restart=50, max_iters=5000, allow_notconv=False,
+                      block=False):
         """GCRO-DR solves of the columns of b one after another, with the
         problem's recycled space of k vectors carried between them (and to
-        later calls, also across set_medium)."""
+        later calls, also across set_medium).  block=True: Block GCRO-DR, the
+        2..16 columns solved together in one block space (iterations are
+        block steps)."""
         import torch
         b = b.contiguous()
         nrhs = b.shape[0]
         x = torch.empty_like(b)
         it = np.zeros(nrhs, np.int32)
         rr = np.zeros(nrhs, np.float64)
-        opts = B.solve_opts(tol, restart, max_iters)
+        opts = B.solve_opts(tol, restart, max_iters,
+                            krylov=B.MXW_KRYLOV_BLOCK if block else B.MXW_KRYLOV_PSEUDOBLOCK)
         st = B.lib().mxw_solve_recycle(self.h, nrhs, b.data_ptr(), C.byref(opts), k, _stream(), x.data_ptr(),
                                        it.ctypes.data, rr.ctypes.data)
         allowed = (B.MXW_OK, B.MXW_ENOTCONV, B.MXW_EBREAKDOWN) if allow_notconv else (B.MXW_OK,)

@@ -363,6 +363,7 @@ struct BlockWork {
 // M^{-1} U beside it, and the small cycle matrices.
 struct RecycleWork {
   int k = 0, m = 0, dim = 0;
+  int p = 1;            // block width the workspace is sized for (Block GCRO-DR)
   int64_t ndof = 0;
   uint64_t gen = 0;   // operator generation C = A Ubar was made for
   DevMem mem;
@@ -375,6 +376,11 @@ struct RecycleWork {
   void* xbuf = nullptr;
   double* host = nullptr;   // pinned
   BlockWork bw;             // Gram products and Cholesky QR
+  // block cycles: coefficients against C of the two passes, the recycled
+  // part of the update, and the block least-squares state
+  double2 *B1 = nullptr, *B2 = nullptr, *Tb = nullptr;
+  double *npb = nullptr, *bnb = nullptr;   // column norms of a block: partials, results
+  BlockWork bb;
   std::vector<double> history;
   int64_t refreshes = 0, deflations = 0, failures = 0;
   ~RecycleWork() {
@@ -385,7 +391,7 @@ struct RecycleWork {
 struct mxw_problem {
   mxw_problem(std::shared_ptr<LayoutShared> s, std::shared_ptr<CtxState> c, hipStream_t st)
       : S(std::move(s)), L(S->L), ctx(c), mem(c, st) {
-    kw.mem.ctx = bw.mem.ctx = rw.mem.ctx = rw.bw.mem.ctx = c;
+    kw.mem.ctx = bw.mem.ctx = rw.mem.ctx = rw.bw.mem.ctx = rw.bb.mem.ctx = c;
   }
   std::shared_ptr<LayoutShared> S;
   const Layout& L;
@@ -1601,28 +1607,94 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
 // Krylov subspace recycling: GCRO-DR over the systems solved on a problem
 // (Sec. 6 proposes it for the slowly varying systems of the imaging loop)
 // ---------------------------------------------------------------------------
-mxw_status ensure_recycle(mxw_problem* P, int k, int m) {
+// Buffers whose size follows the block width p (1 for GCRO-DR, p >= 2 for
+// Block GCRO-DR): [C, V] (m + p vectors), W, R, the preconditioner's
+// staging for max(k, p) columns, the coefficients against C, the column
+// norms and the block least-squares state.  A new width keeps the recycled
+// space: C moves into the new [C, V].
+mxw_status recycle_width(mxw_problem* P, hipStream_t st, int p) {
   RecycleWork& w = P->rw;
   const int64_t n = P->L.ndof;
-  if (w.VC && w.k == k && w.m == m && w.ndof == n) return MXW_OK;
+  const int k = w.k, m = w.m, nblk = red_blocks(n);
+  const bool gath = gathered(P->variant);
+  const int wide = std::max(k, p);   // columns of a preconditioner application
+  std::vector<void*> old = {w.VC, w.W, w.R, w.YS, w.npb, w.bnb, w.B1, w.B2, w.Tb, w.xbuf};
+  double2* VC = w.mem.alloc<double2>((size_t)(m + p) * n);
+  double2* W = w.mem.alloc<double2>((size_t)p * n);
+  double2* R = w.mem.alloc<double2>((size_t)p * n);
+  double2* YS = gath ? w.mem.alloc<double2>((size_t)wide * P->L.sum_ns) : nullptr;
+  double* npb = w.mem.alloc<double>((size_t)p * nblk);
+  double* bnb = w.mem.alloc<double>(p);
+  double2* B1 = w.mem.alloc<double2>((size_t)kRecycleMaxK * p);
+  double2* B2 = w.mem.alloc<double2>((size_t)kRecycleMaxK * p);
+  double2* Tb = w.mem.alloc<double2>((size_t)kRecycleMaxK * p);
+  void* xbuf = nullptr;
+  bool ok = VC && W && R && (!gath || YS) && npb && bnb && B1 && B2 && Tb;
+  if (ok && wide >= 2 && !gath) {
+    const int nchunk = (wide + multi_chunk_cols() - 1) / multi_chunk_cols();
+    xbuf = w.mem.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() * (P->mixed ? 4 : 8));
+    ok = xbuf != nullptr;
+  }
+  if (!ok) {
+    for (void* q : {(void*)VC, (void*)W, (void*)R, (void*)YS, (void*)npb, (void*)bnb, (void*)B1, (void*)B2, (void*)Tb,
+                    xbuf})
+      if (q) w.mem.release(q);
+    set_error("recycling workspace allocation failed");
+    return MXW_ENOMEM;
+  }
+  if (w.VC && w.dim) {
+    HIP_CHECK(hipMemcpyAsync(VC, w.VC, sizeof(double2) * w.dim * n, hipMemcpyDeviceToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  for (void* q : old)
+    if (q) w.mem.release(q);
+  w.VC = VC;
+  w.W = W;
+  w.R = R;
+  w.YS = YS;
+  w.npb = npb;
+  w.bnb = bnb;
+  w.B1 = B1;
+  w.B2 = B2;
+  w.Tb = Tb;
+  w.xbuf = xbuf;
+  w.p = p;
+  return MXW_OK;
+}
+
+// A change of k or m drops the recycled space; a wider block than before
+// grows the width-dependent buffers and keeps it (a narrower one uses them
+// as they are).
+mxw_status ensure_recycle(mxw_problem* P, hipStream_t st, int k, int m, int p = 1) {
+  RecycleWork& w = P->rw;
+  const int64_t n = P->L.ndof;
+  if (w.VC && w.k == k && w.m == m && w.ndof == n) {
+    if (w.p < p) TRY(recycle_width(P, st, p));
+    if (p >= 2) {
+      if (ensure_block_ws(w.bb, n, p, m / p + 1) != MXW_OK) {
+        set_error("recycling workspace allocation failed");
+        return MXW_ENOMEM;
+      }
+    }
+    return MXW_OK;
+  }
   w.mem.reset();
-  w.VC = nullptr;
+  w.bb.mem.reset();
+  w.bb.H1 = nullptr;
+  w.VC = w.W = w.R = w.YS = w.B1 = w.B2 = w.Tb = nullptr;
+  w.npb = w.bnb = nullptr;
+  w.xbuf = nullptr;
   w.dim = 0;
   w.k = k;
   w.m = m;
   w.ndof = n;
   const int maxv = m + 1, nblk = red_blocks(n);
-  const bool gath = gathered(P->variant);
-  w.VC = w.mem.alloc<double2>((size_t)maxv * n);
   w.Zs = w.mem.alloc<double2>((size_t)m * n);
   w.U = w.mem.alloc<double2>((size_t)k * n);
   w.Ub = w.mem.alloc<double2>((size_t)k * n);
   w.Ut = w.mem.alloc<double2>((size_t)k * n);
   w.Ubt = w.mem.alloc<double2>((size_t)k * n);
   w.Ct = w.mem.alloc<double2>((size_t)k * n);
-  w.W = w.mem.alloc<double2>(n);
-  w.R = w.mem.alloc<double2>(n);
-  w.YS = gath ? w.mem.alloc<double2>((size_t)k * P->L.sum_ns) : nullptr;
   w.h1 = w.mem.alloc<double2>(maxv);
   w.h2 = w.mem.alloc<double2>(maxv);
   w.part = w.mem.alloc<double2>((size_t)nblk * maxv);
@@ -1646,17 +1718,15 @@ mxw_status ensure_recycle(mxw_problem* P, int k, int m) {
   w.jd = w.mem.alloc<int>(1);
   w.kd = w.mem.alloc<int>(1);
   w.info = w.mem.alloc<int>(1);
-  w.xbuf = nullptr;
-  bool ok = w.VC && w.Zs && w.U && w.Ub && w.Ut && w.Ubt && w.Ct && w.W && w.R && (!gath || w.YS) && w.h1 && w.h2 &&
-            w.part && w.H && w.sn && w.g && w.y && w.t && w.G && w.WVg && w.UU && w.Mc && w.Mu && w.mu && w.cs &&
-            w.w0 && w.hn && w.npart && w.est && w.beta && w.jd && w.kd && w.info;
-  if (ok && k >= 2 && !gath) {
-    const int nchunk = (k + multi_chunk_cols() - 1) / multi_chunk_cols();
-    w.xbuf = w.mem.alloc<unsigned char>((size_t)nchunk * 2 * P->L.sum_ns * multi_chunk_cols() * (P->mixed ? 4 : 8));
-    ok = w.xbuf != nullptr;
-  }
-  if (ok && !w.host) ok = hipHostMalloc((void**)&w.host, sizeof(double) * 8) == hipSuccess;
+  bool ok = w.Zs && w.U && w.Ub && w.Ut && w.Ubt && w.Ct && w.h1 && w.h2 && w.part && w.H && w.sn && w.g && w.y &&
+            w.t && w.G && w.WVg && w.UU && w.Mc && w.Mu && w.mu && w.cs && w.w0 && w.hn && w.npart && w.est && w.beta &&
+            w.jd && w.kd && w.info;
+  if (ok && !w.host) ok = hipHostMalloc((void**)&w.host, sizeof(double) * (8 + 2 * kRecycleMaxBlockP)) == hipSuccess;
+  // Gram products of the deflation span up to m + p vectors against k
   if (ok) ok = ensure_block_ws(w.bw, n, k, (m + k) / k + 1) == MXW_OK;
+  if (ok) ok = recycle_width(P, st, p) == MXW_OK;
+  // block least squares: at most m / p block steps of p columns
+  if (ok && p >= 2) ok = ensure_block_ws(w.bb, n, p, m / p + 1) == MXW_OK;
   if (!ok) {
     w.mem.reset();
     w.VC = nullptr;
@@ -1704,16 +1774,19 @@ mxw_status recycle_refresh(mxw_problem* P, hipStream_t st) {
 
 // Deflated restart after a cycle with kk recycled vectors and jd Arnoldi
 // steps: the new space from the harmonic Ritz vectors of the cycle.
-mxw_status recycle_deflate(mxw_problem* P, hipStream_t st, int kk, int jd, bool last_row) {
+// jd: Krylov vectors of the cycle (block steps x p); extra: rows of Gbar
+// below kk + jd (1, or 0 after a breakdown, for one right-hand side; p for a
+// block); nw: basis vectors [C, V] projected on U for W^H Vhat.
+mxw_status recycle_deflate(mxw_problem* P, hipStream_t st, int kk, int jd, int extra, int nw) {
   RecycleWork& w = P->rw;
   const int64_t n = P->L.ndof;
   const int s = kk + jd, knew = std::min(w.k, s);
   if (knew == 0) return MXW_OK;
   if (kk) {
-    TRY(gram(w.bw, n, st, w.VC, s + 1, w.U, kk, w.WVg));
+    TRY(gram(w.bw, n, st, w.VC, nw, w.U, kk, w.WVg));
     TRY(gram(w.bw, n, st, w.U, kk, w.U, kk, w.UU));
   }
-  launch_rc_ritz(st, kk, jd, knew, last_row ? 1 : 0, w.G, w.WVg, w.UU, w.Mc, w.Mu, w.mu, w.info);
+  launch_rc_ritz(st, kk, jd, knew, extra, nw, w.G, w.WVg, w.UU, w.Mc, w.Mu, w.mu, w.info);
   HIP_CHECK(hipGetLastError());
   int info = 0;
   HIP_CHECK(hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1723,7 +1796,7 @@ mxw_status recycle_deflate(mxw_problem* P, hipStream_t st, int kk, int jd, bool 
     ++w.failures;
     return MXW_OK;
   }
-  const int rows = s + (last_row ? 1 : 0);
+  const int rows = s + extra;
   const int ld = kRecycleLd;
   TRY(tall_gemm(P, st, w.VC, rows, w.Mc, ld, knew, 1.0, 0.0, w.Ct));
   TRY(tall_gemm(P, st, w.U, kk, w.Mu, ld, knew, 1.0, 0.0, w.Ut));
@@ -1832,7 +1905,7 @@ mxw_status recycle_solve_one(mxw_problem* P, hipStream_t st, const double2* b, d
       launch_rc_by(st, kk, w.jd, w.G, w.y, w.t);
       launch_xupdate(st, n, w.kd, w.Ub, 0, w.t, maxv, x, n, 1);
     }
-    TRY(recycle_deflate(P, st, kk, jdone, !brk));
+    TRY(recycle_deflate(P, st, kk, jdone, brk ? 0 : 1, kk + jdone + 1));
     spmv_dev(P, st, x, w.R, b, 1, nullptr);
     launch_norm(st, n, w.R, n, w.npart, w.beta, 1, nullptr);
     HIP_CHECK(hipGetLastError());
@@ -1847,6 +1920,141 @@ mxw_status recycle_solve_one(mxw_problem* P, hipStream_t st, const double2* b, d
   *iters_out = iters;
   *relres_out = relres;
   if (conv) return MXW_OK;
+  return MXW_ENOTCONV;
+}
+
+// Block GCRO-DR: the p columns of B solved together with the problem's
+// recycled space (Sec. 6: block and recycling strategies combined).  A cycle
+// removes the block residual's part in range(C), runs block Arnoldi for
+// (I - C C^H) A M^{-1} (block CGS2 against C and the previous blocks,
+// Cholesky QR of each new block, the block Householder least squares of
+// block GMRES), updates X += Z Y - Ubar (B Y) and replaces the space by the
+// harmonic Ritz vectors of the cycle (Gbar with p rows below the Krylov
+// part).  Iterations count block steps.
+mxw_status recycle_solve_block(mxw_problem* P, hipStream_t st, int p, const double2* B, double2* X,
+                               const mxw_solve_opts* opts, int32_t* iters_out, double* relres_out) {
+  RecycleWork& w = P->rw;
+  BlockWork& b = w.bb;
+  const int64_t n = P->L.ndof;
+  const int m = w.m, mb = b.m, ldE = (mb + 1) * p;
+  double* hb = w.host;
+  auto norms = [&](const double2* A, std::vector<double>& out) -> mxw_status {
+    launch_norm(st, n, A, n, w.npb, w.bnb, p, nullptr);
+    HIP_CHECK(hipMemcpyAsync(hb, w.bnb, sizeof(double) * p, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    out.assign(hb, hb + p);
+    return MXW_OK;
+  };
+  std::vector<double> bn, rn(p, 1.0), est;
+  TRY(norms(B, bn));
+  for (int c = 0; c < p; ++c)
+    if (!(bn[c] > 0)) {
+      set_error("block recycling needs non-zero right-hand sides");
+      return MXW_EINVAL;
+    }
+  w.history.clear();
+  if (w.dim && w.gen != P->op_gen) TRY(recycle_refresh(P, st));
+  HIP_CHECK(hipMemsetAsync(X, 0, sizeof(double2) * n * p, st));
+  HIP_CHECK(hipMemcpyAsync(w.R, B, sizeof(double2) * n * p, hipMemcpyDeviceToDevice, st));
+  auto below = [&](const std::vector<double>& v) {
+    for (int c = 0; c < p; ++c)
+      if (!(v[c] <= opts->tol * bn[c])) return false;
+    return true;
+  };
+  int steps = 0;
+  bool conv = false, bad = false;
+  while (true) {
+    const int kk = w.dim;
+    if (kk) {   // minimal residual correction over range(U): T = C^H R
+      TRY(gram(b, n, st, w.VC, kk, w.R, p, w.Tb));
+      TRY(tall_gemm(P, st, w.Ub, kk, w.Tb, kk, p, 1.0, 1.0, X));
+      TRY(tall_gemm(P, st, w.VC, kk, w.Tb, kk, p, -1.0, 1.0, w.R));
+    }
+    std::vector<double> pn;
+    TRY(norms(w.R, pn));
+    if (below(pn)) {   // verify with the true residual
+      launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, X, n, w.W, n, B, n, p, nullptr);
+      TRY(norms(w.W, rn));
+      if (below(rn)) {
+        conv = true;
+        break;
+      }
+    }
+    const int nb = std::max(1, (m - kk) / p);
+    double2* V = w.VC + (int64_t)kk * n;   // the cycle's blocks follow C
+    TRY(cholqr2(P, b, st, w.R, w.W, V, p));
+    launch_set_e(st, p, ldE, b.S, b.E);
+    int jd = 0;
+    for (int j = 0; j < nb; ++j) {
+      double2* Vj = V + (int64_t)j * p * n;
+      double2* Zj = w.Zs + (int64_t)j * p * n;
+      const int Q = (j + 1) * p;
+      apply_prec_dev(P, st, Vj, n, Zj, n, p, nullptr, w.YS, w.xbuf);
+      {
+        ScopedKernelTimer tm("spmv");
+        launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, Zj, n, w.W, n, nullptr, 0, p, nullptr);
+      }
+      for (int pass = 0; pass < 2; ++pass) {   // against C, then the previous blocks; twice
+        double2* Bp = pass ? w.B2 : w.B1;
+        double2* Hp = pass ? b.H2 : b.H1;
+        if (kk) {
+          TRY(gram(b, n, st, w.VC, kk, w.W, p, Bp));
+          TRY(tall_gemm(P, st, w.VC, kk, Bp, kk, p, -1.0, 1.0, w.W));
+        }
+        TRY(gram(b, n, st, V, Q, w.W, p, Hp));
+        TRY(tall_gemm(P, st, V, Q, Hp, Q, p, -1.0, 1.0, w.W));
+      }
+      TRY(cholqr2(P, b, st, w.W, w.R, V + (int64_t)Q * n, p));
+      launch_rc_save_block(st, kk, j, p, w.B1, w.B2, b.H1, b.H2, b.S, w.G);
+      launch_bls_step(st, j, p, mb, b.H1, b.H2, b.S, b.Hc, b.T, b.Rls, b.E, b.est);
+      HIP_CHECK(hipGetLastError());
+      HIP_CHECK(hipMemcpyAsync(hb, b.est, sizeof(double) * p, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      est.assign(hb, hb + p);
+      ++steps;
+      jd = j + 1;
+      double worst = 0.0;
+      for (int c = 0; c < p; ++c) {
+        worst = std::max(worst, est[c] / bn[c]);
+        if (!std::isfinite(est[c])) bad = true;
+      }
+      w.history.push_back(worst);
+      if (below(est) || bad || steps >= opts->max_iters) break;
+    }
+    if (bad) break;
+    // X += Z Y - Ubar (B Y)
+    const int q = jd * p;
+    launch_bls_solve(st, q, p, mb, b.Rls, b.E, b.Y);
+    TRY(tall_gemm(P, st, w.Zs, q, b.Y, mb * p, p, 1.0, 1.0, X));
+    if (kk) {
+      launch_rc_by_block(st, kk, q, p, w.G, b.Y, mb * p, w.Tb);
+      TRY(tall_gemm(P, st, w.Ub, kk, w.Tb, kk, p, 1.0, 1.0, X));
+    }
+    TRY(recycle_deflate(P, st, kk, q, p, kk + q + p));
+    launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, X, n, w.R, n, B, n, p, nullptr);
+    HIP_CHECK(hipGetLastError());
+    TRY(norms(w.R, rn));
+    if (below(rn)) {
+      conv = true;
+      break;
+    }
+    bool finite = true;
+    for (double v : rn) finite = finite && std::isfinite(v);
+    if (steps >= opts->max_iters || !finite) {
+      bad = bad || !finite;
+      break;
+    }
+  }
+  for (int c = 0; c < p; ++c) {
+    if (iters_out) iters_out[c] = steps;
+    if (relres_out) relres_out[c] = rn[c] / bn[c];
+  }
+  if (conv) return MXW_OK;
+  if (bad) {
+    set_error("block recycling: non-finite values before the tolerance");
+    return MXW_EBREAKDOWN;
+  }
+  set_error("max_iters reached before the tolerance");
   return MXW_ENOTCONV;
 }
 
@@ -2485,7 +2693,8 @@ mxw_status mxw_problem_device_bytes(const mxw_problem* P, uint64_t* bytes) {
     set_error("bytes is NULL");
     return MXW_EINVAL;
   }
-  *bytes = P->mem.bytes + P->kw.mem.bytes + P->bw.mem.bytes + P->rw.mem.bytes + P->rw.bw.mem.bytes;
+  *bytes = P->mem.bytes + P->kw.mem.bytes + P->bw.mem.bytes + P->rw.mem.bytes + P->rw.bw.mem.bytes +
+           P->rw.bb.mem.bytes;
   return MXW_OK;
 }
 
@@ -2725,7 +2934,15 @@ mxw_status mxw_solve_recycle(mxw_problem* P, int32_t nrhs, const double* b_dev, 
   }
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> hold(P->run);
-  TRY(ensure_recycle(P, k, opts->restart));
+  if (opts->krylov == MXW_KRYLOV_BLOCK && nrhs >= 2) {
+    if (nrhs > kRecycleMaxBlockP || opts->restart + nrhs > kRecycleLd) {
+      set_error("block recycling takes 2..16 right-hand sides and restart + nrhs <= 65");
+      return MXW_EINVAL;
+    }
+    TRY(ensure_recycle(P, st, k, opts->restart, nrhs));
+    return recycle_solve_block(P, st, nrhs, (const double2*)b_dev, (double2*)x_dev, opts, iters_out, relres_out);
+  }
+  TRY(ensure_recycle(P, st, k, opts->restart));
   const int64_t n = P->L.ndof;
   mxw_status result = MXW_OK;
   bool brk = false;

@@ -196,9 +196,14 @@ void launch_xupdate(hipStream_t st, int64_t ndof, const int* jd, const double2* 
 constexpr int kRecycleMaxCycle = 64;   // largest recycled + Arnoldi vectors per cycle
 constexpr int kRecycleLd = kRecycleMaxCycle + 1;
 constexpr int kRecycleMaxK = 32;       // largest recycled dimension
+constexpr int kRecycleMaxBlockP = 16;  // widest block of Block GCRO-DR
 void launch_rc_save(hipStream_t st, int kk, int j, const double2* h, const double* hn, double2* G);
 void launch_rc_by(hipStream_t st, int kk, const int* jd, const double2* G, const double2* y, double2* t);
-void launch_rc_ritz(hipStream_t st, int kk, int jd, int knew, int last_row, const double2* G, const double2* WVg,
-                    const double2* UU, double2* Mc, double2* Mu, double2* mu, int* info);
+void launch_rc_ritz(hipStream_t st, int kk, int jd, int knew, int extra, int ldw, const double2* G,
+                    const double2* WVg, const double2* UU, double2* Mc, double2* Mu, double2* mu, int* info);
+void launch_rc_save_block(hipStream_t st, int kk, int j, int p, const double2* B1, const double2* B2,
+                          const double2* H1, const double2* H2, const double2* S, double2* G);
+void launch_rc_by_block(hipStream_t st, int kk, int q, int p, const double2* G, const double2* Y, int ldy,
+                        double2* T);
 
 }  // namespace mxw

@@ -119,18 +119,19 @@ __global__ void k_rc_by(int kk, const int* __restrict__ jd, const double2* __res
 
 // The deflated restart of one cycle (one workgroup of 256 threads).
 //   G:   Gbar columns kk .. s-1 (ld kRcLd), columns < kk implied by D
-//   WVg: [C, V_0..V_jd]^H U  ((s + 1) x kk, ld s + 1)     (kk > 0)
+//   WVg: [C, V_0..V_jd]^H U  ((s + extra) x kk, ld ldw)  (kk > 0)
 //   UU:  U^H U  (kk x kk)                                   (kk > 0)
-//   last_row: 1 to include V_jd (0 after a breakdown, where it is not a
-//   basis vector)
+//   extra: rows of Gbar below s -- 1 for one right-hand side (0 after a
+//   breakdown, where V_jd is not a basis vector), p for a block of p
 // Outputs (ld kRcLd): Mc ((s + 1) x knew) with C_new = [C, V] Mc, and
 // Mu (s x knew) with U_new = [U, V] Mu (D folded into its first kk rows);
 // mu: the s values 1/theta, selected ones first; info[0] = 1 when the Schur
 // iteration did not converge or a pivot vanished.
-__global__ void __launch_bounds__(256) k_rc_ritz(int kk, int jd, int knew, int last_row, const double2* __restrict__ G,
-                                                 const double2* __restrict__ WVg, const double2* __restrict__ UU,
-                                                 double2* __restrict__ Mc, double2* __restrict__ Mu,
-                                                 double2* __restrict__ mu, int* __restrict__ info) {
+__global__ void __launch_bounds__(256) k_rc_ritz(int kk, int jd, int knew, int extra, int ldw,
+                                                 const double2* __restrict__ G, const double2* __restrict__ WVg,
+                                                 const double2* __restrict__ UU, double2* __restrict__ Mc,
+                                                 double2* __restrict__ Mu, double2* __restrict__ mu,
+                                                 int* __restrict__ info) {
   __shared__ double2 A1[kRcMax * kRcLd];   // Gbar -> R -> Schur vectors
   __shared__ double2 A2[kRcMax * kRcLd];   // WV -> S -> Schur form -> Gbar P -> Qk
   __shared__ double2 Rk[kRcK * kRcK];
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(256) k_rc_ritz(int kk, int jd, int knew, int l
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int s = kk + jd;
-  const int rows = s + (last_row ? 1 : 0);
+  const int rows = s + extra;
   const double2 zero = make_double2(0.0, 0.0);
   if (tid == 0) bad = 0;
   for (int c = tid; c < kk; c += blockDim.x) dsc[c] = 1.0 / sqrt(fmax(UU[c * kk + c].x, 1e-300));
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(256) k_rc_ritz(int kk, int jd, int knew, int l
     if (c < s && i < rows) {
       if (c < kk) {
         g = (i == c) ? make_double2(dsc[c], 0.0) : zero;
-        w = cscale(WVg[(int64_t)c * (s + 1) + i], dsc[c]);
+        w = cscale(WVg[(int64_t)c * ldw + i], dsc[c]);
       } else {
         g = G[(int64_t)c * kRcLd + i];
         w = (i == c) ? make_double2(1.0, 0.0) : zero;
@@ -450,9 +451,54 @@ void launch_rc_by(hipStream_t st, int kk, const int* jd, const double2* G, const
   hipLaunchKernelGGL(k_rc_by, dim3(1), dim3(64), 0, st, kk, jd, G, y, t);
 }
 
-void launch_rc_ritz(hipStream_t st, int kk, int jd, int knew, int last_row, const double2* G, const double2* WVg,
-                    const double2* UU, double2* Mc, double2* Mu, double2* mu, int* info) {
-  hipLaunchKernelGGL(k_rc_ritz, dim3(1), dim3(256), 0, st, kk, jd, knew, last_row, G, WVg, UU, Mc, Mu, mu, info);
+void launch_rc_ritz(hipStream_t st, int kk, int jd, int knew, int extra, int ldw, const double2* G,
+                    const double2* WVg, const double2* UU, double2* Mc, double2* Mu, double2* mu, int* info) {
+  hipLaunchKernelGGL(k_rc_ritz, dim3(1), dim3(256), 0, st, kk, jd, knew, extra, ldw, G, WVg, UU, Mc, Mu, mu, info);
+}
+
+// Block cycles (p right-hand sides): columns kk + j p .. kk + (j+1) p - 1 of
+// Gbar from block step j: rows < kk the coefficients against C (B1 + B2, two
+// Gram-Schmidt passes, ld kk), rows kk .. kk + (j+1) p - 1 those against
+// the previous blocks (H1 + H2, ld (j+1) p), the next p rows the new block's
+// triangular factor S (p x p), the rest zero.
+__global__ void k_rc_save_block(int kk, int j, int p, const double2* __restrict__ B1, const double2* __restrict__ B2,
+                                const double2* __restrict__ H1, const double2* __restrict__ H2,
+                                const double2* __restrict__ S, double2* __restrict__ G) {
+  const int c = blockIdx.x;   // column of the block step, < p
+  const int q = (j + 1) * p;
+  for (int i = threadIdx.x; i < kRcLd; i += blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    if (i < kk) {
+      v = cadd(B1[(int64_t)c * kk + i], B2[(int64_t)c * kk + i]);
+    } else if (i < kk + q) {
+      const int r = i - kk;
+      v = cadd(H1[(int64_t)c * q + r], H2[(int64_t)c * q + r]);
+    } else if (i < kk + q + p) {
+      v = S[(int64_t)c * p + (i - kk - q)];
+    }
+    G[(int64_t)(kk + j * p + c) * kRcLd + i] = v;
+  }
+}
+
+void launch_rc_save_block(hipStream_t st, int kk, int j, int p, const double2* B1, const double2* B2,
+                          const double2* H1, const double2* H2, const double2* S, double2* G) {
+  hipLaunchKernelGGL(k_rc_save_block, dim3(p), dim3(64), 0, st, kk, j, p, B1, B2, H1, H2, S, G);
+}
+
+// T (kk x p, ld kk) = -B Y: the recycled part of a block cycle's update;
+// B = rows < kk of Gbar's columns kk .. kk + q - 1, Y (q x p, ld ldy).
+__global__ void k_rc_by_block(int kk, int q, int p, const double2* __restrict__ G, const double2* __restrict__ Y,
+                              int ldy, double2* __restrict__ T) {
+  const int c = blockIdx.x, i = threadIdx.x;
+  if (i >= kk) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int l = 0; l < q; ++l) acc = cadd(acc, cmul(G[(int64_t)(kk + l) * kRcLd + i], Y[(int64_t)c * ldy + l]));
+  T[(int64_t)c * kk + i] = make_double2(-acc.x, -acc.y);
+}
+
+void launch_rc_by_block(hipStream_t st, int kk, int q, int p, const double2* G, const double2* Y, int ldy,
+                        double2* T) {
+  if (kk > 0) hipLaunchKernelGGL(k_rc_by_block, dim3(p), dim3(64), 0, st, kk, q, p, G, Y, ldy, T);
 }
 
 }  // namespace mxw

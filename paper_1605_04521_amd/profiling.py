@@ -28,10 +28,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # kernel key -> (name pattern, source file)
 KERNELS = {
-    "lu": (r"k_lu<", "lu_kernels.hip"),
+    "lu": (r"k_lu(_queue)?<", "lu_kernels.hip"),
     "local_solve_multi": (r"k_local_solve_multi(_tall)?<", "multi_solve.hip"),
     "local_solve": (r"k_local_solve<", "solve_kernels.hip"),
-    "spmv": (r"k_sp(mv|mm)<", "solve_kernels.hip"),
+    "spmv": (r"k_sp(mv|mm)(_il)?[<(]", "solve_kernels.hip"),
 }
 
 
@@ -117,6 +117,7 @@ def main(argv=None):
     b.add_argument("--write", required=True)
     b.add_argument("--precision", required=True)
     b.add_argument("--nrhs", type=int, required=True)
+    b.add_argument("--nsub", default="", help="partition of the run (part of the record's key)")
     b.add_argument("--out", required=True)
     b.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args(argv)
@@ -129,7 +130,7 @@ def main(argv=None):
         with open(args.out) as f:
             data = json.load(f)
     for key, rec in res.items():
-        data[f"{key}|{args.precision}|{args.nrhs}"] = rec
+        data[f"{key}|{args.precision}|{args.nrhs}" + (f"|{args.nsub}" if args.nsub else "")] = rec
     with open(args.out, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     json.dump(res, sys.stdout, indent=1)

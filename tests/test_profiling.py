@@ -21,6 +21,9 @@ def test_kernel_key_mapping():
     assert profiling.kernel_key("void mxw::k_local_solve<double, 32>(...)") == "local_solve"
     assert profiling.kernel_key("void mxw::k_spmm<16, 8>(...)") == "spmv"
     assert profiling.kernel_key("void mxw::k_spmv<16>(...)") == "spmv"
+    assert profiling.kernel_key("mxw::k_spmm_il(long, int, ...)") == "spmv"
+    assert profiling.kernel_key("void mxw::k_lu_queue<float, 32, 8>(float*, ...)") == "lu"
+    assert profiling.kernel_key("mxw::k_to_interleaved(long, int, ...)") is None
     assert profiling.kernel_key("mxw::k_dots(...)") is None
 
 
