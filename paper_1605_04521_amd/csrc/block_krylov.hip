@@ -1,7 +1,8 @@
 // Block flexible GMRES over one shared Krylov space for all right-hand sides
 // (the block solver of Sec. 5): the products with the tall n x (j+1)p bases
 // (split-K Gram matrices V^H W and their fixed-order reduction, the updates
-// W -= V H and X += Z Y) on MFMA, the Cholesky factor of a Gram matrix (the
+// W -= V H and X += Z Y) on MFMA with three real products per complex
+// product, the Cholesky factor of a Gram matrix (the
 // block QR of a new basis block is a Cholesky QR applied twice), the
 // Householder update of the block Hessenberg least-squares problem, and its
 // back substitution.
@@ -65,7 +66,7 @@ constexpr int kGramChunkStep = 32;   // n entries staged per LDS step
 // the workgroups sharing a chunk's strip of W are launched together; the four
 // waves of a workgroup take 16 rows q each; the W and V strips of every
 // 32-entry step are staged in LDS with coalesced loads.
-__global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
+__global__ void __launch_bounds__(256, 3) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
                                                int p, int64_t n, int64_t chunk, double2* __restrict__ part,
                                                const int* __restrict__ cond) {
   if (cond && !*cond) return;   // a step's optional work, decided on the device
@@ -76,8 +77,10 @@ __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int64_t i0 = (int64_t)blockIdx.y * chunk, i1 = min(n, i0 + chunk);
   const int q0 = blockIdx.x * 64;
-  acc_t cre[2], cim[2];
-  for (int t = 0; t < 2; ++t) cre[t] = cim[t] = acc_t{0, 0, 0, 0};
+  // conj(a) b by three real products (Gauss): P1 = ar br, P2 = ai bi,
+  // P3 = (ar - ai)(br + bi); Re = P1 + P2, Im = P3 - P1 + P2
+  acc_t p1[2], p2[2], p3[2];
+  for (int t = 0; t < 2; ++t) p1[t] = p2[t] = p3[t] = acc_t{0, 0, 0, 0};
   // the strips of the next step are loaded into registers while the current
   // step's products run
   double2 pv[64 * S / 256], pw[kMaxBlockP * S / 256];
@@ -112,14 +115,13 @@ __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, in
 #pragma unroll
     for (int k0 = 0; k0 < S; k0 += 4) {
       const double2 a = Vs[wave * 16 + li][k0 + lk];
+      const double ad = a.x - a.y;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const double2 b = Ws[t * 16 + li][k0 + lk];
-        // conj(a) b
-        cre[t] = Mfma<double>::op(a.x, b.x, cre[t]);
-        cre[t] = Mfma<double>::op(a.y, b.y, cre[t]);
-        cim[t] = Mfma<double>::op(a.x, b.y, cim[t]);
-        cim[t] = Mfma<double>::op(-a.y, b.x, cim[t]);
+        p1[t] = Mfma<double>::op(a.x, b.x, p1[t]);
+        p2[t] = Mfma<double>::op(a.y, b.y, p2[t]);
+        p3[t] = Mfma<double>::op(ad, b.x + b.y, p3[t]);
       }
     }
     __syncthreads();
@@ -130,7 +132,7 @@ __global__ void __launch_bounds__(256) k_bgram(const double2* __restrict__ V, in
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int q = q0 + wave * 16 + Mfma<double>::row(lane, v), b = t * 16 + li;
-      if (q < Q && b < p) out[(int64_t)b * Q + q] = make_double2(cre[t][v], cim[t][v]);
+      if (q < Q && b < p) out[(int64_t)b * Q + q] = make_double2(p1[t][v] + p2[t][v], p3[t][v] - p1[t][v] + p2[t][v]);
     }
 }
 
@@ -150,18 +152,20 @@ int bgram_parts(int64_t n, int nchunks) {
 // M column-major K x p with leading dimension ldm.  Formed as out^T = M^T A^T:
 // each wave owns 32 b x 32 i (lanes run along i, so loads of A and stores of
 // out are coalesced); a workgroup covers 128 entries i.  out may be C.
-__global__ void __launch_bounds__(256) k_bupdate(const double2* __restrict__ A, int K, const double2* __restrict__ M,
+__global__ void __launch_bounds__(256, 2) k_bupdate(const double2* __restrict__ A, int K, const double2* __restrict__ M,
                                                  int ldm, int p, int64_t n, double alpha, double beta,
                                                  const double2* C, double2* out, const int* __restrict__ cond) {
   if (cond && !*cond) return;   // a step's optional work, decided on the device
   typedef Mfma<double>::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int64_t ibase = (int64_t)blockIdx.x * 128 + wave * 32;
-  acc_t dre[2][2], dim[2][2];
+  // m a by three real products (Gauss): P1 = mr ar, P2 = mi ai,
+  // P3 = (mr + mi)(ar + ai); Re = P1 - P2, Im = P3 - P1 - P2
+  acc_t p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) dre[t][u] = dim[t][u] = acc_t{0, 0, 0, 0};
+    for (int u = 0; u < 2; ++u) p1[t][u] = p2[t][u] = p3[t][u] = acc_t{0, 0, 0, 0};
   for (int q0 = 0; q0 < K; q0 += 16) {
     // four 4-wide k steps: every load issued before the products
     double2 m[4][2], a[4][2];
@@ -181,16 +185,22 @@ __global__ void __launch_bounds__(256) k_bupdate(const double2* __restrict__ A, 
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4)
+    for (int s4 = 0; s4 < 4; ++s4) {
+      double ms[2], as[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        ms[q] = m[s4][q].x + m[s4][q].y;
+        as[q] = a[s4][q].x + a[s4][q].y;
+      }
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          dre[t][u] = Mfma<double>::op(m[s4][t].x, a[s4][u].x, dre[t][u]);
-          dre[t][u] = Mfma<double>::op(-m[s4][t].y, a[s4][u].y, dre[t][u]);
-          dim[t][u] = Mfma<double>::op(m[s4][t].x, a[s4][u].y, dim[t][u]);
-          dim[t][u] = Mfma<double>::op(m[s4][t].y, a[s4][u].x, dim[t][u]);
+          p1[t][u] = Mfma<double>::op(m[s4][t].x, a[s4][u].x, p1[t][u]);
+          p2[t][u] = Mfma<double>::op(m[s4][t].y, a[s4][u].y, p2[t][u]);
+          p3[t][u] = Mfma<double>::op(ms[t], as[u], p3[t][u]);
         }
+    }
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -201,7 +211,8 @@ __global__ void __launch_bounds__(256) k_bupdate(const double2* __restrict__ A, 
         const int b = t * 16 + Mfma<double>::row(lane, v);
         const int64_t i = ibase + u * 16 + li;
         if (b < p && i < n) {
-          double2 r = make_double2(alpha * dre[t][u][v], alpha * dim[t][u][v]);
+          const double re = p1[t][u][v] - p2[t][u][v], im = p3[t][u][v] - p1[t][u][v] - p2[t][u][v];
+          double2 r = make_double2(alpha * re, alpha * im);
           if (beta != 0.0) {
             const double2 c = C[(int64_t)b * n + i];
             r.x += beta * c.x;

@@ -230,7 +230,12 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
 // the first half's new solutions (K = those 64 rows, read back from X), then
 // the same three-block triangular step.  LDS: the 128-row T block, the
 // diagonal inverse and coupling blocks (the second diagonal inverse waits in
-// registers for the first one's slot); solutions overwrite their T rows.
+// registers for the first one's LDS slot); solutions overwrite their T rows.
+// In the long product the four waves multiply the same rows of X into their
+// own factor rows, so X goes through LDS once per workgroup: strips of 4*KU
+// rows, double-buffered in the space of the triangular blocks (unused
+// then), the next strip loaded while the current one is multiplied; each
+// complex product there takes three real MFMA products instead of four.
 template <typename R, int NB, int PC, int KU>
 __global__ void __launch_bounds__(256, 3) k_local_solve_multi_tall(
     const R* __restrict__ F, const int64_t* __restrict__ foff, const int* __restrict__ nsz,
@@ -241,8 +246,18 @@ __global__ void __launch_bounds__(256, 3) k_local_solve_multi_tall(
   static_assert(NB == 32 && PC == 32, "tile shape assumes 32 x 32 blocks");
   constexpr int SB = 4 * NB, HB = 2 * NB;   // rows per pass, rows per half
   typedef typename Mfma<R>::acc_t acc_t;
+  // X strips in LDS: KS rows of X per strip, stored per column with the
+  // rows in MFMA operand order (row 4u + lk at lk*KU + u, so a lane's KU
+  // operands are contiguous), XLD entries per column (padded: the 16-byte
+  // reads of a wave spread evenly over the banks)
+  constexpr int KS = 4 * KU, XLD = KS + 4, EL = 16 / sizeof(R), LPT = KS * PC / EL / 256;
+  static_assert(LPT >= 1 && KS * PC == LPT * EL * 256, "a strip is a whole number of 16-byte loads per thread");
+  constexpr int kBlk = 2 * 2 * NB * (NB + 1), kStrip = 2 * 2 * PC * XLD;
   __shared__ R Tr[SB][PC + 1], Ti[SB][PC + 1];
-  __shared__ R Br[2][NB][NB + 1], Bi[2][NB][NB + 1];   // [0] diagonal inverse, [1] coupling block
+  // [0] diagonal inverse, [1] coupling block of both planes; the strips
+  __shared__ __attribute__((aligned(16))) R Bsh[kBlk > kStrip ? kBlk : kStrip];
+  R(*Br)[NB][NB + 1] = reinterpret_cast<R(*)[NB][NB + 1]>(Bsh);
+  R(*Bi)[NB][NB + 1] = reinterpret_cast<R(*)[NB][NB + 1]>(Bsh + 2 * NB * (NB + 1));
   const int s = order ? order[blockIdx.x] : blockIdx.x;
   const int chunk = blockIdx.y, c0 = chunk * PC;
   const int n = nsz[s];
@@ -294,23 +309,96 @@ __global__ void __launch_bounds__(256, 3) k_local_solve_multi_tall(
       // K range ([0, r0) forward, [r0 + rn, n) backward)
       const int k_lo = sweep == 0 ? 0 : r0 + rn, k_hi = sweep == 0 ? r0 : n;
       {
-        acc_t pre[2][2], pim[2][2];
+        // complex products by three real ones (Gauss): P1 = Ar Xr, P2 = Ai Xi,
+        // P3 = (Ar + Ai)(Xr + Xi); Re = P1 - P2, Im = P3 - P1 - P2
+        acc_t p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            pre[rt][ct] = acc_t{0, 0, 0, 0};
-            pim[rt][ct] = acc_t{0, 0, 0, 0};
-          }
+          for (int ct = 0; ct < 2; ++ct) p1[rt][ct] = p2[rt][ct] = p3[rt][ct] = acc_t{0, 0, 0, 0};
         bool row_ok[2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) row_ok[rt] = wave * NB + rt * 16 + li < rn;
         const int arow = r0 + wave * NB + li;
-        for (int k0 = k_lo; k0 < k_hi; k0 += 4 * KU) {
-          Slice<R, KU, PC> sl;
-          sl.load(fr, fi, xrr, xir, (int)ld, arow, row_ok, k0, k_hi, lk, li);
-          __builtin_amdgcn_sched_barrier(0);
-          sl.product(pre, pim);
+        typedef unsigned v4u __attribute__((ext_vector_type(4)));
+        v4u gr[LPT], gi[LPT];   // the next strip in flight
+        auto fetch = [&](int kb) {
+#pragma unroll
+          for (int l = 0; l < LPT; ++l) {
+            const int e = (tid + 256 * l) * EL, kk = kb + e / PC;
+            const int o = kk < k_hi ? (kk * PC + e % PC) * (int)sizeof(R) : kOob;
+            gr[l] = __builtin_amdgcn_raw_buffer_load_b128(xrr, o, 0, 0);
+            gi[l] = __builtin_amdgcn_raw_buffer_load_b128(xir, o, 0, 0);
+          }
+        };
+        auto stash = [&](int buf) {
+          R* sr = Bsh + buf * 2 * PC * XLD;
+          R* si = sr + PC * XLD;
+#pragma unroll
+          for (int l = 0; l < LPT; ++l) {
+            const int e = (tid + 256 * l) * EL, kk = e / PC, c = e % PC;
+            const int pos = (kk & 3) * KU + (kk >> 2);
+            R vr[EL], vi[EL];
+            __builtin_memcpy(vr, &gr[l], 16);
+            __builtin_memcpy(vi, &gi[l], 16);
+#pragma unroll
+            for (int j = 0; j < EL; ++j) {
+              sr[(c + j) * XLD + pos] = vr[j];
+              si[(c + j) * XLD + pos] = vi[j];
+            }
+          }
+        };
+        const int nst = (k_hi - k_lo + KS - 1) / KS;
+        if (nst > 0) {
+          fetch(k_lo);
+          stash(0);
+        }
+        __syncthreads();
+        for (int t = 0; t < nst; ++t) {
+          const int kb = k_lo + t * KS;
+          R ar[2][KU], ai[2][KU];
+#pragma unroll
+          for (int u = 0; u < KU; ++u) {
+            const int kk = kb + 4 * u + lk;
+            const int fo = (kk * (int)ld + arow) * (int)sizeof(R);
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+              const int o = (kk < k_hi && row_ok[rt]) ? fo + rt * 16 * (int)sizeof(R) : kOob;
+              ar[rt][u] = BufLoad<R>::at(fr, o);
+              ai[rt][u] = BufLoad<R>::at(fi, o);
+            }
+          }
+          if (t + 1 < nst) fetch(kb + KS);
+          const R* sr = Bsh + (t & 1) * 2 * PC * XLD;
+          const R* si = sr + PC * XLD;
+          R xr[2][KU], xi[2][KU];
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+              xr[ct][u] = sr[(ct * 16 + li) * XLD + lk * KU + u];
+              xi[ct][u] = si[(ct * 16 + li) * XLD + lk * KU + u];
+            }
+#pragma unroll
+          for (int u = 0; u < KU; ++u) {
+            R as[2], xs[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              as[q] = ar[q][u] + ai[q][u];
+              xs[q] = xr[q][u] + xi[q][u];
+            }
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+              for (int ct = 0; ct < 2; ++ct) {
+                p1[rt][ct] = Mfma<R>::op(ar[rt][u], xr[ct][u], p1[rt][ct]);
+                p2[rt][ct] = Mfma<R>::op(ai[rt][u], xi[ct][u], p2[rt][ct]);
+                p3[rt][ct] = Mfma<R>::op(as[rt], xs[ct], p3[rt][ct]);
+              }
+          }
+          // the buffer written now was last read before the previous barrier
+          if (t + 1 < nst) stash((t + 1) & 1);
+          __syncthreads();
         }
         // T = X rows of the pass - product (each wave its own rows)
 #pragma unroll
@@ -328,8 +416,8 @@ __global__ void __launch_bounds__(256, 3) k_local_solve_multi_tall(
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int r = wave * NB + rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
-              Tr[r][c] -= pre[rt][ct][q];
-              Ti[r][c] -= pim[rt][ct][q];
+              Tr[r][c] -= p1[rt][ct][q] - p2[rt][ct][q];
+              Ti[r][c] -= p3[rt][ct][q] - p1[rt][ct][q] - p2[rt][ct][q];
             }
         __syncthreads();
       }
