@@ -65,18 +65,21 @@ constexpr int kGramChunkStep = 32;   // n entries staged per LDS step
 // conj(V[q][i]) W[b][i], q < Q, b < p <= 32.  Grid (ceil(Q/64), chunks), so
 // the workgroups sharing a chunk's strip of W are launched together; the four
 // waves of a workgroup take 16 rows q each; the W and V strips of every
-// 32-entry step are staged in LDS with coalesced loads.
+// 32-entry step are staged in LDS with coalesced loads.  (Keeping a chunk's
+// workgroups on one XCD, so that its strip of W is fetched into one L2
+// instead of several, measured slower: 10.3 -> 10.9 ms at 1,600 rows.)
 __global__ void __launch_bounds__(256, 3) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
                                                int p, int64_t n, int64_t chunk, double2* __restrict__ part,
                                                const int* __restrict__ cond) {
   if (cond && !*cond) return;   // a step's optional work, decided on the device
+  const int ch = blockIdx.y, qt = blockIdx.x;
   typedef Mfma<double>::acc_t acc_t;
   constexpr int S = kGramChunkStep;
   __shared__ double2 Vs[64][S + 1];
   __shared__ double2 Ws[kMaxBlockP][S + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.y * chunk, i1 = min(n, i0 + chunk);
-  const int q0 = blockIdx.x * 64;
+  const int64_t i0 = (int64_t)ch * chunk, i1 = min(n, i0 + chunk);
+  const int q0 = qt * 64;
   // conj(a) b by three real products (Gauss): P1 = ar br, P2 = ai bi,
   // P3 = (ar - ai)(br + bi); Re = P1 + P2, Im = P3 - P1 + P2
   acc_t p1[2], p2[2], p3[2];
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(256, 3) k_bgram(const double2* __restrict__ V,
     }
     __syncthreads();
   }
-  double2* out = part + (int64_t)blockIdx.y * Q * p;
+  double2* out = part + (int64_t)ch * Q * p;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -136,10 +139,63 @@ __global__ void __launch_bounds__(256, 3) k_bgram(const double2* __restrict__ V,
     }
 }
 
+// Split-K partials of the p x p Gram matrix W^H W (p <= 32): the strip of W
+// is staged once per step (the general kernel would stage it twice and leave
+// half of its waves without rows); wave w forms the 16 x 16 tile (rows
+// (w & 1) * 16, columns (w >> 1) * 16).  Same partial layout.
+__global__ void __launch_bounds__(256) k_bgram_self(const double2* __restrict__ W, int p, int64_t n, int64_t chunk,
+                                                    double2* __restrict__ part, const int* __restrict__ cond) {
+  if (cond && !*cond) return;   // a step's optional work, decided on the device
+  typedef Mfma<double>::acc_t acc_t;
+  constexpr int S = kGramChunkStep;
+  __shared__ double2 Ws[kMaxBlockP][S + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int qt = wave & 1, bt = wave >> 1;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  acc_t p1 = acc_t{0, 0, 0, 0}, p2 = p1, p3 = p1;
+  double2 pw[kMaxBlockP * S / 256];
+  auto fetch = [&](int64_t is) {
+#pragma unroll
+    for (int u = 0; u < kMaxBlockP * S / 256; ++u) {
+      const int idx = tid + 256 * u, r = idx / S, k = idx % S;
+      const int64_t i = is + k;
+      pw[u] = (r < p && i < i1) ? W[(int64_t)r * n + i] : make_double2(0.0, 0.0);
+    }
+  };
+  if (i0 < i1) fetch(i0);
+  for (int64_t is = i0; is < i1; is += S) {
+#pragma unroll
+    for (int u = 0; u < kMaxBlockP * S / 256; ++u) {
+      const int idx = tid + 256 * u;
+      Ws[idx / S][idx % S] = pw[u];
+    }
+    __syncthreads();
+    if (is + S < i1) fetch(is + S);
+#pragma unroll
+    for (int k0 = 0; k0 < S; k0 += 4) {
+      const double2 a = Ws[qt * 16 + li][k0 + lk], b = Ws[bt * 16 + li][k0 + lk];
+      p1 = Mfma<double>::op(a.x, b.x, p1);
+      p2 = Mfma<double>::op(a.y, b.y, p2);
+      p3 = Mfma<double>::op(a.x - a.y, b.x + b.y, p3);
+    }
+    __syncthreads();
+  }
+  double2* out = part + (int64_t)blockIdx.x * p * p;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int q = qt * 16 + Mfma<double>::row(lane, v), b = bt * 16 + li;
+    if (q < p && b < p) out[(int64_t)b * p + q] = make_double2(p1[v] + p2[v], p3[v] - p1[v] + p2[v]);
+  }
+}
+
 void launch_bgram(hipStream_t st, const double2* V, int Q, const double2* W, int p, int64_t n, int nchunks,
                   double2* part, const int* cond) {
   const int64_t chunk = ((n + nchunks - 1) / nchunks + kGramChunkStep - 1) / kGramChunkStep * kGramChunkStep;
   const int used = (int)((n + chunk - 1) / chunk);
+  if (V == W && Q == p) {
+    hipLaunchKernelGGL(k_bgram_self, dim3(used), dim3(256), 0, st, W, p, n, chunk, part, cond);
+    return;
+  }
   hipLaunchKernelGGL(k_bgram, dim3((Q + 63) / 64, used), dim3(256), 0, st, V, Q, W, p, n, chunk, part, cond);
 }
 
@@ -150,15 +206,23 @@ int bgram_parts(int64_t n, int nchunks) {
 
 // out[b][i] = beta C[b][i] + alpha sum_q A[q][i] M[q][b] for b < p <= 32, q < K;
 // M column-major K x p with leading dimension ldm.  Formed as out^T = M^T A^T:
-// each wave owns 32 b x 32 i (lanes run along i, so loads of A and stores of
-// out are coalesced); a workgroup covers 128 entries i.  out may be C.
+// a workgroup covers 128 entries i, each wave 32 b x 32 i (lanes run along i,
+// so the stores of out are coalesced).  Per step of 16 q the workgroup stages
+// the 16 x 128 tile of A (rows of 2 KB, coalesced) and the 16 x p tile of M
+// (read once per workgroup instead of once per wave) in LDS; the next step's
+// tiles are loaded into registers while the current one is multiplied.  out
+// may be C.
 __global__ void __launch_bounds__(256, 2) k_bupdate(const double2* __restrict__ A, int K, const double2* __restrict__ M,
                                                  int ldm, int p, int64_t n, double alpha, double beta,
                                                  const double2* C, double2* out, const int* __restrict__ cond) {
   if (cond && !*cond) return;   // a step's optional work, decided on the device
   typedef Mfma<double>::acc_t acc_t;
+  constexpr int KS = 16, IW = 128;
+  constexpr int LA = KS * IW / 256, LM = KS * kMaxBlockP / 256;
+  __shared__ double2 As[KS][IW + 1];
+  __shared__ double2 Ms[KS][kMaxBlockP + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-  const int64_t ibase = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int64_t i0 = (int64_t)blockIdx.x * IW;
   // m a by three real products (Gauss): P1 = mr ar, P2 = mi ai,
   // P3 = (mr + mi)(ar + ai); Re = P1 - P2, Im = P3 - P1 - P2
   acc_t p1[2][2], p2[2][2], p3[2][2];
@@ -166,42 +230,60 @@ __global__ void __launch_bounds__(256, 2) k_bupdate(const double2* __restrict__ 
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u) p1[t][u] = p2[t][u] = p3[t][u] = acc_t{0, 0, 0, 0};
-  for (int q0 = 0; q0 < K; q0 += 16) {
-    // four 4-wide k steps: every load issued before the products
-    double2 m[4][2], a[4][2];
+  double2 pa[LA], pm[LM];
+  auto fetch = [&](int q0) {
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int q = q0 + 4 * s4 + lk;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int b = t * 16 + li;
-        m[s4][t] = (q < K && b < p) ? M[(int64_t)b * ldm + q] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int64_t i = ibase + u * 16 + li;
-        a[s4][u] = (q < K && i < n) ? A[(int64_t)q * n + i] : make_double2(0.0, 0.0);
-      }
+    for (int u = 0; u < LA; ++u) {
+      const int idx = tid + 256 * u, r = idx / IW, c = idx % IW;
+      const int q = q0 + r;
+      const int64_t i = i0 + c;
+      pa[u] = (q < K && i < n) ? A[(int64_t)q * n + i] : make_double2(0.0, 0.0);
     }
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
+    for (int u = 0; u < LM; ++u) {   // consecutive threads along q of one column of M
+      const int idx = tid + 256 * u, b = idx / KS, r = idx % KS;
+      const int q = q0 + r;
+      pm[u] = (q < K && b < p) ? M[(int64_t)b * ldm + q] : make_double2(0.0, 0.0);
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int q0 = 0; q0 < K; q0 += KS) {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int idx = tid + 256 * u;
+      As[idx / IW][idx % IW] = pa[u];
+    }
+#pragma unroll
+    for (int u = 0; u < LM; ++u) {
+      const int idx = tid + 256 * u;
+      Ms[idx % KS][idx / KS] = pm[u];
+    }
+    __syncthreads();
+    if (q0 + KS < K) fetch(q0 + KS);
+#pragma unroll
+    for (int s4 = 0; s4 < KS / 4; ++s4) {
+      const int r = 4 * s4 + lk;
+      double2 m[2], a[2];
       double ms[2], as[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        ms[q] = m[s4][q].x + m[s4][q].y;
-        as[q] = a[s4][q].x + a[s4][q].y;
+        m[q] = Ms[r][q * 16 + li];
+        a[q] = As[r][wave * 32 + q * 16 + li];
+        ms[q] = m[q].x + m[q].y;
+        as[q] = a[q].x + a[q].y;
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          p1[t][u] = Mfma<double>::op(m[s4][t].x, a[s4][u].x, p1[t][u]);
-          p2[t][u] = Mfma<double>::op(m[s4][t].y, a[s4][u].y, p2[t][u]);
+          p1[t][u] = Mfma<double>::op(m[t].x, a[u].x, p1[t][u]);
+          p2[t][u] = Mfma<double>::op(m[t].y, a[u].y, p2[t][u]);
           p3[t][u] = Mfma<double>::op(ms[t], as[u], p3[t][u]);
         }
     }
+    __syncthreads();
   }
+  const int64_t ibase = i0 + wave * 32;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
