@@ -345,6 +345,7 @@ struct BlockWork {
           *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *S = nullptr, *T = nullptr, *Rls = nullptr, *E = nullptr,
           *Y = nullptr;
   double2* Xi = nullptr;   // interleaved copy of a block for the product with A (p >= 16)
+  double2* Vi = nullptr;   // interleaved copy of a basis block for the local solves' gather (p >= 16)
   double* est = nullptr;
   int* info = nullptr;   // [0] rank loss, [1] second Gram-Schmidt pass needed
   int64_t reorth = 0;    // second passes in the last solve
@@ -614,7 +615,7 @@ uint64_t block_bytes(int64_t n, int p, int m) {
   b += nbytes_of<double2>((size_t)m * p * m * p);                      // Rls
   b += nbytes_of<double2>(Q * p) + nbytes_of<double2>((size_t)m * p * p);   // E, Y
   b += nbytes_of<double>(p) + nbytes_of<int>(2);                       // est, info
-  if (p >= kIlMinCols) b += nbytes_of<double2>((size_t)n * interleaved_cols());   // Xi
+  if (p >= kIlMinCols) b += 2 * nbytes_of<double2>((size_t)n * interleaved_cols());   // Xi, Vi
   return b;
 }
 
@@ -697,12 +698,14 @@ mxw_status ensure_krylov(mxw_problem* P, int nrhs, int m) {
 }
 
 // z = M^{-1} v for ncol columns (device, stride ndof)
+// vil (optional): the interleaved copy of v, gathered by the multi-column
+// solves instead of v (at most interleaved_cols() columns)
 void apply_prec_dev(mxw_problem* P, hipStream_t st, const double2* v, int64_t vstride, double2* z, int64_t zstride,
-                    int ncol, const int* active, double2* ys, void* xbuf = nullptr) {
+                    int ncol, const int* active, double2* ys, void* xbuf = nullptr, const double2* vil = nullptr) {
   if (xbuf && ncol >= 2 && !gathered(P->variant)) {
     ScopedKernelTimer tm("local_solve_multi");
     LocalSolveArgs a{P->L.n_sub, (int)P->L.max_ns, P->foff, P->nsz, P->lds, P->perm, P->poff, P->sub_dofs, P->pou,
-                     P->order};
+                     P->order, vil};
     if (P->mixed)
       launch_local_solve_multi<float>(st, a, (const float*)P->F, v, vstride, z, zstride, (float*)xbuf, P->L.sum_ns,
                                       ncol, active, P->multi_ku, P->multi_rows);
@@ -1375,8 +1378,9 @@ mxw_status ensure_block_ws(BlockWork& b, int64_t n, int p, int m, bool with_xi =
   b.est = b.mem.alloc<double>(p);
   b.info = b.mem.alloc<int>(2);
   b.Xi = want_xi ? b.mem.alloc<double2>((size_t)n * interleaved_cols()) : nullptr;
+  b.Vi = want_xi ? b.mem.alloc<double2>((size_t)n * interleaved_cols()) : nullptr;
   if (!b.H1 || !b.H2 || !b.Hc || !b.part || !b.G || !b.G0 || !b.R1 || !b.R1i || !b.R2 || !b.R2i || !b.S || !b.T || !b.Rls ||
-      !b.E || !b.Y || !b.est || !b.info || (want_xi && !b.Xi)) {
+      !b.E || !b.Y || !b.est || !b.info || (want_xi && (!b.Xi || !b.Vi))) {
     b.H1 = nullptr;
     set_error("block Krylov workspace: " + b.mem.why);
     return MXW_ENOMEM;
@@ -1481,7 +1485,12 @@ mxw_status block_solve(mxw_problem* P, int p, const double2* B, const mxw_solve_
       // than 1 - 1/sqrt(2) of its norm in the first (flag b.info[1], read by
       // the kernels of that pass), Cholesky QR twice, the least-squares update
       auto step = [&](hipStream_t s) -> mxw_status {
-        apply_prec_dev(P, s, Vj, n, Zj, n, p, nullptr, k.YS, k.xbuf);
+        if (b.Vi && !gathered(P->variant)) {   // the local solves gather whole rows of the block
+          launch_to_interleaved(s, n, p, Vj, n, b.Vi);
+          apply_prec_dev(P, s, Vj, n, Zj, n, p, nullptr, k.YS, k.xbuf, b.Vi);
+        } else {
+          apply_prec_dev(P, s, Vj, n, Zj, n, p, nullptr, k.YS, k.xbuf);
+        }
         block_spmv(P, s, Zj, k.W, nullptr, p);
         TRY(gram(P, s, k.W, p, k.W, p, b.G0));
         TRY(gram(P, s, k.V, Q, k.W, p, b.H1));

@@ -126,6 +126,10 @@ struct LocalSolveArgs {
   const int* sub_dofs;
   const uint8_t* pou;
   const int* order;
+  // optional interleaved copy of the input ([ndof][interleaved_cols()],
+  // zero-padded columns): the multi-column solves gather a row's columns as
+  // one contiguous read (at most interleaved_cols() columns)
+  const double2* vil = nullptr;
 };
 template <typename R>
 void launch_local_solve(hipStream_t st, const LocalSolveArgs& a, const R* F, const double2* v, int64_t vstride,
@@ -172,6 +176,9 @@ void launch_spmm_interleaved(hipStream_t st, int64_t n, int p, const int64_t* ro
                              const double2* vals, const double2* x, int64_t xstride, double2* xi, double2* y,
                              int64_t ystride, const double2* b, int64_t bstride);
 int interleaved_cols();
+// xi[j][c] = x[c][j] for the p <= interleaved_cols() columns (stride xstride),
+// columns p.. zero
+void launch_to_interleaved(hipStream_t st, int64_t n, int p, const double2* x, int64_t xstride, double2* xi);
 
 int red_blocks(int64_t ndof);
 void launch_dots(hipStream_t st, int64_t ndof, int nvec, const double2* V, int64_t vcol, const double2* w,

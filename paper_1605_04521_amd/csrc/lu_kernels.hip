@@ -114,14 +114,14 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
         }
       }
     }
-    acc_t pre[2][2], pim[2][2];
+    // FP32: three real products per complex product (Slice::product3); FP64
+    // keeps four (the third accumulator set would spill): p1, p2 = Re, Im
+    constexpr bool k3 = sizeof(R) == 4;
+    acc_t p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        pre[rt][ct] = acc_t{0, 0, 0, 0};
-        pim[rt][ct] = acc_t{0, 0, 0, 0};
-      }
+      for (int ct = 0; ct < 2; ++ct) p1[rt][ct] = p2[rt][ct] = p3[rt][ct] = acc_t{0, 0, 0, 0};
     bool row_ok[2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) row_ok[rt] = rh * NB + rt * 16 + li < rn;
@@ -130,7 +130,10 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
       Slice<R, KU, PC> sl;
       sl.load(fr, fi, xrr, xir, ld, arow, row_ok, k0, k_hi, lk, li);
       __builtin_amdgcn_sched_barrier(0);
-      sl.product(pre, pim);
+      if constexpr (k3)
+        sl.product3(p1, p2, p3);
+      else
+        sl.product(p1, p2);
     }
     // T = the block of the column (rows r0.., columns j0..j0+kb) - product
 #pragma unroll
@@ -174,8 +177,13 @@ __device__ void update_block_column(SweepSmem<R, NB>& sm, int n, int ld, int j0,
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int r = rh * NB + rt * 16 + Mfma<R>::row(lane, q), c = ct * 16 + li;
-              sm.Tr[r][c] -= pre[rt][ct][q];
-              sm.Ti[r][c] -= pim[rt][ct][q];
+              if constexpr (k3) {
+                sm.Tr[r][c] -= p1[rt][ct][q] - p2[rt][ct][q];
+                sm.Ti[r][c] -= p3[rt][ct][q] - p1[rt][ct][q] - p2[rt][ct][q];
+              } else {
+                sm.Tr[r][c] -= p1[rt][ct][q];
+                sm.Ti[r][c] -= p2[rt][ct][q];
+              }
             }
       }
       __syncthreads();

@@ -24,8 +24,8 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
     const R* __restrict__ F, const int64_t* __restrict__ foff, const int* __restrict__ nsz,
     const int* __restrict__ lds, const int* __restrict__ perm, const int64_t* __restrict__ poff,
     const int* __restrict__ sub_dofs, const uint8_t* __restrict__ pou, const double2* __restrict__ v, int64_t vstride,
-    double2* __restrict__ z, int64_t zstride, R* __restrict__ xbuf, int64_t xchunk, int ncol,
-    const int* __restrict__ active, const int* __restrict__ order) {
+    const double2* __restrict__ vil, double2* __restrict__ z, int64_t zstride, R* __restrict__ xbuf, int64_t xchunk,
+    int ncol, const int* __restrict__ active, const int* __restrict__ order) {
   static_assert(NB == 32 && PC == 32, "tile shape assumes 32 x 32 blocks");
   constexpr int SB = 2 * NB;   // rows per pass over the factor
   typedef typename Mfma<R>::acc_t acc_t;
@@ -59,7 +59,8 @@ __global__ void __launch_bounds__(256) k_local_solve_multi(
       a[u] = make_double2(0.0, 0.0);
       if (idx < n * PC) {
         const int i = idx / PC, col = c0 + idx % PC;
-        if (col < ncol) a[u] = v[(int64_t)col * vstride + D[P[i]]];
+        if (col < ncol)   // the interleaved copy: a row's columns in one contiguous read
+          a[u] = vil ? vil[(int64_t)D[P[i]] * PC + idx % PC] : v[(int64_t)col * vstride + D[P[i]]];
       }
     }
 #pragma unroll
@@ -241,8 +242,8 @@ __global__ void __launch_bounds__(256, 3) k_local_solve_multi_tall(
     const R* __restrict__ F, const int64_t* __restrict__ foff, const int* __restrict__ nsz,
     const int* __restrict__ lds, const int* __restrict__ perm, const int64_t* __restrict__ poff,
     const int* __restrict__ sub_dofs, const uint8_t* __restrict__ pou, const double2* __restrict__ v, int64_t vstride,
-    double2* __restrict__ z, int64_t zstride, R* __restrict__ xbuf, int64_t xchunk, int ncol,
-    const int* __restrict__ active, const int* __restrict__ order) {
+    const double2* __restrict__ vil, double2* __restrict__ z, int64_t zstride, R* __restrict__ xbuf, int64_t xchunk,
+    int ncol, const int* __restrict__ active, const int* __restrict__ order) {
   static_assert(NB == 32 && PC == 32, "tile shape assumes 32 x 32 blocks");
   constexpr int SB = 4 * NB, HB = 2 * NB;   // rows per pass, rows per half
   typedef typename Mfma<R>::acc_t acc_t;
@@ -283,7 +284,8 @@ __global__ void __launch_bounds__(256, 3) k_local_solve_multi_tall(
       a[u] = make_double2(0.0, 0.0);
       if (idx < n * PC) {
         const int i = idx / PC, col = c0 + idx % PC;
-        if (col < ncol) a[u] = v[(int64_t)col * vstride + D[P[i]]];
+        if (col < ncol)   // the interleaved copy: a row's columns in one contiguous read
+          a[u] = vil ? vil[(int64_t)D[P[i]] * PC + idx % PC] : v[(int64_t)col * vstride + D[P[i]]];
       }
     }
 #pragma unroll
@@ -577,20 +579,22 @@ void launch_local_solve_multi(hipStream_t st, const LocalSolveArgs& a, const R* 
   if (a.n_sub == 0 || ncol == 0) return;
   const int nchunk = (ncol + kMultiPC - 1) / kMultiPC;
   const int64_t xchunk = 2 * sum_ns * kMultiPC;
+  static_assert(kMultiPC == 32, "the interleaved copy holds 32 columns per unknown");
+  const double2* vil = ncol <= kMultiPC ? a.vil : nullptr;
   // ku: 4-wide k steps per K slice of the long product; rows: rows per pass
   // over the factor (64, or 128 with 8-wide slices) -- tuning choices
   if (rows == 128)
     timed_launch(k_local_solve_multi_tall<R, kLuNB, kMultiPC, 8>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F,
-                 a.foff, a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol,
-                 active, a.order);
+                 a.foff, a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, vil, z, zstride, xbuf, xchunk,
+                 ncol, active, a.order);
   else if (ku == 4)
     timed_launch(k_local_solve_multi<R, kLuNB, kMultiPC, 4>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F, a.foff,
-                 a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol, active,
-                 a.order);
+                 a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, vil, z, zstride, xbuf, xchunk, ncol,
+                 active, a.order);
   else
     timed_launch(k_local_solve_multi<R, kLuNB, kMultiPC, 8>, dim3(a.n_sub, nchunk), dim3(256), 0, st, F, a.foff,
-                 a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, z, zstride, xbuf, xchunk, ncol, active,
-                 a.order);
+                 a.nsz, a.lds, a.perm, a.poff, a.sub_dofs, a.pou, v, vstride, vil, z, zstride, xbuf, xchunk, ncol,
+                 active, a.order);
 }
 template void launch_local_solve_multi<double>(hipStream_t, const LocalSolveArgs&, const double*, const double2*,
                                                int64_t, double2*, int64_t, double*, int64_t, int, const int*, int,

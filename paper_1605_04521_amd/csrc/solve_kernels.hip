@@ -688,8 +688,14 @@ void launch_spmm_interleaved(hipStream_t st, int64_t n, int p, const int64_t* ro
                              int64_t ystride, const double2* b, int64_t bstride) {
   if (n == 0 || p == 0) return;
   const unsigned nb = (unsigned)((n + kIlRows - 1) / kIlRows);
-  hipLaunchKernelGGL(k_to_interleaved, dim3(nb), dim3(256), 0, st, n, p, x, xstride, xi);
+  if (x) hipLaunchKernelGGL(k_to_interleaved, dim3(nb), dim3(256), 0, st, n, p, x, xstride, xi);
   timed_launch(k_spmm_il, dim3(nb), dim3(256), 0, st, n, p, rowptr, cols, vals, xi, y, ystride, b, bstride);
+}
+
+void launch_to_interleaved(hipStream_t st, int64_t n, int p, const double2* x, int64_t xstride, double2* xi) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_to_interleaved, dim3((unsigned)((n + kIlRows - 1) / kIlRows)), dim3(256), 0, st, n, p, x,
+                     xstride, xi);
 }
 
 int interleaved_cols() { return kIlCols; }

@@ -98,6 +98,28 @@ struct Slice {
       }
     }
   }
+  // The same products by three real ones (Gauss): P1 += Ar Xr, P2 += Ai Xi,
+  // P3 += (Ar + Ai)(Xr + Xi); the product is P1 - P2 + i (P3 - P1 - P2).
+  template <typename Acc>
+  __device__ __forceinline__ void product3(Acc (&p1)[2][2], Acc (&p2)[2][2], Acc (&p3)[2][2]) const {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      R as[2], xs[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        as[q] = ar[q][u] + ai[q][u];
+        xs[q] = xr[q][u] + xi[q][u];
+      }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          p1[rt][ct] = Mfma<R>::op(ar[rt][u], xr[ct][u], p1[rt][ct]);
+          p2[rt][ct] = Mfma<R>::op(ai[rt][u], xi[ct][u], p2[rt][ct]);
+          p3[rt][ct] = Mfma<R>::op(as[rt], xs[ct], p3[rt][ct]);
+        }
+    }
+  }
   template <typename Acc>
   __device__ __forceinline__ void product(Acc (&pre)[2][2], Acc (&pim)[2][2]) const {
 #pragma unroll

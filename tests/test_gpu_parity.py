@@ -514,13 +514,18 @@ def test_tile_choices_agree(precision):
             assert t["multi_tall_ms"] <= min(t["multi_ms"])
     assert t["lu_launch"] in (1, 2) and min(t["lu_launch_ms"]) > 0
     assert t["lu_launch_ms"][t["lu_launch"] - 1] == min(t["lu_launch_ms"])
-    # both k slice widths of the LU (FP32 factors; FP64 always takes 4)
+    # both k slice widths of the LU (FP32 factors; FP64 always takes 4).  Two
+    # FP32 factorisations that group the block-column products differently
+    # differ by FP32 rounding amplified by the conditioning of A_s (measured
+    # 1.0e-5 relative in the application with the three-product update),
+    # hence the looser bar for FP32 factors
+    tol_lu = 1e-12 if precision == B.MXW_FP64 else 5e-5
     Q = Problem.from_problem(prob, precision=precision, defer_factor=True)
     Q.set_tiles(lu_ku=4)
     Q.factor()
     Zq = to_np(Q.apply_prec(Vt))
     for c in range(33):
-        assert np.linalg.norm(Zq[c] - Z0[c]) <= tol * np.linalg.norm(Z0[c]), c
+        assert np.linalg.norm(Zq[c] - Z0[c]) <= tol_lu * np.linalg.norm(Z0[c]), c
     # both LU launches (one workgroup per subdomain, persistent queue) give the
     # same factors bit for bit
     Zl = {}
