@@ -459,6 +459,32 @@ void launch_set_e(hipStream_t st, int p, int ldE, const double2* S0, double2* E)
 //      I - 2 v v^H / (v^H v) with v_0 chosen so that the diagonal is
 //      -e^{i arg x_0} |x|; Q_j^H = H_{p-1} ... H_0 stored in T_j;
 //   4. E window <- Q_j^H E window; R column block stored; est = row norms.
+// Out (p2 x p) = Qt (p2 x p2) In (p2 x p) in LDS, p2 = 2p <= 64: thread t
+// forms row t % 64 for the columns of group t / 64 (p / 4 columns), so a
+// wave reads In[k][c] as a broadcast and each Qt[r][k] once per k; every
+// output sums k = 0..p2-1 in order.
+__device__ __forceinline__ void window_product(int p, int p2, const double2 (*Qt)[2 * kMaxBlockP + 1],
+                                               const double2 (*In)[kMaxBlockP + 1], double2 (*Out)[kMaxBlockP + 1]) {
+  constexpr int CG = kMaxBlockP / 4;   // columns per thread
+  const int r = threadIdx.x & 63, c0 = (threadIdx.x >> 6) * CG;
+  if (r >= p2 || c0 >= p) return;
+  double sr[CG], si[CG];
+#pragma unroll
+  for (int u = 0; u < CG; ++u) sr[u] = si[u] = 0.0;
+  for (int k = 0; k < p2; ++k) {
+    const double2 a = Qt[r][k];
+#pragma unroll
+    for (int u = 0; u < CG; ++u) {
+      const double2 b = In[k][c0 + u];
+      sr[u] += a.x * b.x - a.y * b.y;
+      si[u] += a.x * b.y + a.y * b.x;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < CG; ++u)
+    if (c0 + u < p) Out[r][c0 + u] = make_double2(sr[u], si[u]);
+}
+
 __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const double2* __restrict__ H1,
                                                   const double2* __restrict__ H2in, const double2* __restrict__ S,
                                                   double2* __restrict__ Hc, double2* __restrict__ T,
@@ -471,6 +497,7 @@ __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const dou
   __shared__ double2 B[2 * kMaxBlockP][kMaxBlockP + 1];
   __shared__ double2 Qt[2 * kMaxBlockP][2 * kMaxBlockP + 1];
   __shared__ double2 vh[2 * kMaxBlockP];
+  __shared__ double2 wsh[3 * kMaxBlockP];
   __shared__ double tau_s, red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p2 = 2 * p, ld = (m + 1) * p, Q = (j + 1) * p, ldR = m * p;
@@ -505,16 +532,7 @@ __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const dou
       Qt[r][c] = T[(int64_t)i * p2 * p2 + idx];
     }
     __syncthreads();
-    for (int idx = tid; idx < p2 * p; idx += 256) {
-      const int r = idx % p2, c = idx / p2;
-      double sr = 0.0, si = 0.0;
-      for (int k = 0; k < p2; ++k) {
-        const double2 a = Qt[r][k], b = A[k][c];
-        sr += a.x * b.x - a.y * b.y;
-        si += a.x * b.y + a.y * b.x;
-      }
-      B[r][c] = make_double2(sr, si);
-    }
+    window_product(p, p2, Qt, A, B);
     __syncthreads();
     for (int idx = tid; idx < p2 * p; idx += 256) {
       const int r = idx % p2, c = idx / p2;
@@ -563,31 +581,36 @@ __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const dou
     }
     __syncthreads();
     const double tau = tau_s;
-    // apply to the remaining columns of A and to every column of Qt
-    for (int c = tid; c < p + p2; c += 256) {
-      double2* col = nullptr;
-      bool isA = c < p;
-      if (isA && c <= k) continue;
-      double wr = 0.0, wi = 0.0;   // w = v^H col
-      for (int r = k; r < p2; ++r) {
-        const double2 x = isA ? A[r][c] : Qt[r][c - p];
-        wr += vh[r].x * x.x + vh[r].y * x.y;
-        wi += vh[r].x * x.y - vh[r].y * x.x;
+    // apply to the remaining columns of A and to every column of Qt:
+    // w_c = tau v^H col_c, one column per wave at a time (lanes along the
+    // rows, wave reduction), then col_c -= v w_c by all threads
+    for (int c = wave; c < p + p2; c += 4) {
+      const bool isA = c < p;
+      if (isA && c <= k) continue;   // uniform over the wave
+      double wr = 0.0, wi = 0.0;
+      if (lane >= k && lane < p2) {
+        const double2 x = isA ? A[lane][c] : Qt[lane][c - p];
+        const double2 v = vh[lane];
+        wr = v.x * x.x + v.y * x.y;
+        wi = v.x * x.y - v.y * x.x;
       }
-      wr *= tau;
-      wi *= tau;
-      for (int r = k; r < p2; ++r) {
-        const double2 v = vh[r];
-        const double dr = v.x * wr - v.y * wi, di = v.x * wi + v.y * wr;
-        if (isA) {
-          A[r][c].x -= dr;
-          A[r][c].y -= di;
-        } else {
-          Qt[r][c - p].x -= dr;
-          Qt[r][c - p].y -= di;
-        }
+      wr = wave_sum(wr);
+      wi = wave_sum(wi);
+      if (lane == 0) wsh[c] = make_double2(tau * wr, tau * wi);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < (p2 - k) * (p + p2); idx += 256) {
+      const int r = k + idx % (p2 - k), c = idx / (p2 - k);
+      if (c < p && c <= k) continue;
+      const double2 v = vh[r], w = wsh[c];
+      const double dr = v.x * w.x - v.y * w.y, di = v.x * w.y + v.y * w.x;
+      if (c < p) {
+        A[r][c].x -= dr;
+        A[r][c].y -= di;
+      } else {
+        Qt[r][c - p].x -= dr;
+        Qt[r][c - p].y -= di;
       }
-      (void)col;
     }
     __syncthreads();
     if (tid == 0) {
@@ -612,18 +635,7 @@ __global__ void __launch_bounds__(256) k_bls_step(int j, int p, int m, const dou
     B[r][c] = E[(int64_t)c * ld + j * p + r];
   }
   __syncthreads();
-  {
-    for (int idx = tid; idx < p2 * p; idx += 256) {
-      const int r = idx % p2, c = idx / p2;
-      double sr = 0.0, si = 0.0;
-      for (int k = 0; k < p2; ++k) {
-        const double2 a = Qt[r][k], b = B[k][c];
-        sr += a.x * b.x - a.y * b.y;
-        si += a.x * b.y + a.y * b.x;
-      }
-      A[r][c] = make_double2(sr, si);
-    }
-  }
+  window_product(p, p2, Qt, B, A);
   __syncthreads();
   for (int idx = tid; idx < p2 * p; idx += 256) {
     const int r = idx % p2, c = idx / p2;
