@@ -399,7 +399,11 @@ def serve_bench(args):
     warm = [Request(rid=-1 - j, arrival=0.0, mesh=k, eps=catalogue[k].eps, sources=ring[:1], precision=B.MXW_MIXED)
             for j, k in enumerate(keys)]
     Server(backend, budget=budget, slots=4).run(warm, realtime=False)
-    server = Server(backend, budget=budget, slots=4)
+    def finished(r):   # one line per completed request (the run's progress)
+        state = "failed" if r.error else f"{len(r.sources)} sources, {r.reused}"
+        log(f"[serve] request {r.rid} on {r.mesh} done at {r.finish:.1f}s ({state})")
+
+    server = Server(backend, budget=budget, slots=4, on_finish=finished)
     wall = server.run(reqs, realtime=True, deadline=args.duration or None)
     done = [r for r in reqs if r.error is None and r.finish is not None]
     bad = [r for r in done if r.relres is None or np.max(r.relres) > 1e-8]

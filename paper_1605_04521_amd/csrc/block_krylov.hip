@@ -654,33 +654,63 @@ void launch_bls_step(hipStream_t st, int j, int p, int m, const double2* H1, con
 }
 
 // Y = R^{-1} E[0:jp, :] (R = Rls[0:jp, 0:jp], upper); Y has leading dimension m p.
+// Blocked from the bottom: a 32-row diagonal block is solved in LDS (one
+// thread per column), then every row above takes the block's contribution
+// in one parallel product (the rows of R read coalesced).
 __global__ void __launch_bounds__(256) k_bls_solve(int jp, int p, int m, const double2* __restrict__ Rls,
                                                    const double2* __restrict__ E, double2* __restrict__ Y) {
+  constexpr int BS = 32;
+  __shared__ double2 Rb[BS][BS + 1];
+  __shared__ double2 Yb[BS][kMaxBlockP + 1];
   const int tid = threadIdx.x, ldR = m * p, ldE = (m + 1) * p;
   for (int idx = tid; idx < jp * p; idx += 256) {
     const int r = idx % jp, c = idx / jp;
     Y[(int64_t)c * ldR + r] = E[(int64_t)c * ldE + r];
   }
   __syncthreads();
-  __shared__ double2 q[kMaxBlockP];
-  for (int i = jp - 1; i >= 0; --i) {
-    // Y[i][c] /= R[i][i]; then Y[0:i][c] -= R[0:i][i] Y[i][c]
-    if (tid < p) {
-      const double2 d = Rls[(int64_t)i * ldR + i];
-      const double dd = d.x * d.x + d.y * d.y;
-      const double2 yi = Y[(int64_t)tid * ldR + i];
-      // a zero diagonal (a direction the block never reached) takes no weight
-      const double2 v = dd > 0.0 ? make_double2((yi.x * d.x + yi.y * d.y) / dd, (yi.y * d.x - yi.x * d.y) / dd)
-                                 : make_double2(0.0, 0.0);
-      Y[(int64_t)tid * ldR + i] = v;
-      q[tid] = v;
+  for (int b1 = jp; b1 > 0; b1 -= BS) {
+    const int b0 = max(0, b1 - BS), nb = b1 - b0;
+    for (int idx = tid; idx < nb * nb; idx += 256) {
+      const int r = idx % nb, c = idx / nb;
+      Rb[r][c] = Rls[(int64_t)(b0 + c) * ldR + b0 + r];
+    }
+    for (int idx = tid; idx < nb * p; idx += 256) {
+      const int r = idx % nb, c = idx / nb;
+      Yb[r][c] = Y[(int64_t)c * ldR + b0 + r];
     }
     __syncthreads();
-    for (int idx = tid; idx < i * p; idx += 256) {
-      const int r = idx % i, c = idx / i;
-      const double2 a = Rls[(int64_t)i * ldR + r], v = q[c];
-      Y[(int64_t)c * ldR + r].x -= a.x * v.x - a.y * v.y;
-      Y[(int64_t)c * ldR + r].y -= a.x * v.y + a.y * v.x;
+    if (tid < p) {
+      for (int i = nb - 1; i >= 0; --i) {
+        const double2 d = Rb[i][i];
+        const double dd = d.x * d.x + d.y * d.y;
+        const double2 yi = Yb[i][tid];
+        // a zero diagonal (a direction the block never reached) takes no weight
+        const double2 v = dd > 0.0 ? make_double2((yi.x * d.x + yi.y * d.y) / dd, (yi.y * d.x - yi.x * d.y) / dd)
+                                   : make_double2(0.0, 0.0);
+        Yb[i][tid] = v;
+        for (int r = 0; r < i; ++r) {
+          const double2 a = Rb[r][i];
+          Yb[r][tid].x -= a.x * v.x - a.y * v.y;
+          Yb[r][tid].y -= a.x * v.y + a.y * v.x;
+        }
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nb * p; idx += 256) {
+      const int r = idx % nb, c = idx / nb;
+      Y[(int64_t)c * ldR + b0 + r] = Yb[r][c];
+    }
+    for (int idx = tid; idx < b0 * p; idx += 256) {
+      const int r = idx % b0, c = idx / b0;
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < nb; ++k) {
+        const double2 a = Rls[(int64_t)(b0 + k) * ldR + r], v = Yb[k][c];
+        sr += a.x * v.x - a.y * v.y;
+        si += a.x * v.y + a.y * v.x;
+      }
+      double2& y = Y[(int64_t)c * ldR + r];
+      y.x -= sr;
+      y.y -= si;
     }
     __syncthreads();
   }

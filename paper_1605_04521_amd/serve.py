@@ -253,10 +253,11 @@ class Server:
     one host loop admits requests, starts their solves asynchronously and
     collects them as they complete."""
 
-    def __init__(self, backend, budget: int, slots: int = 4, poll_s: float = 0.002):
+    def __init__(self, backend, budget: int, slots: int = 4, poll_s: float = 0.002, on_finish=None):
         self.backend = backend
         self.sched = Scheduler(backend, budget, slots)
         self.poll_s = poll_s
+        self.on_finish = on_finish       # called with each request as it completes (or fails)
 
     def run(self, requests, realtime: bool = True, deadline: float = None):
         """Returns the wall time of the run.  deadline (seconds): requests not
@@ -291,6 +292,8 @@ class Server:
                     req.finish = time.perf_counter() - t0
                     self.backend.release(req, run)
                     self.sched.done()
+                    if self.on_finish:
+                        self.on_finish(req)
             still = []
             for req, run in running:
                 if not self.backend.poll(run):
@@ -303,6 +306,8 @@ class Server:
                 req.finish = time.perf_counter() - t0
                 self.backend.release(req, run)
                 self.sched.done()
+                if self.on_finish:
+                    self.on_finish(req)
             running = still
             if i >= len(pending) and not self.sched.waiting and not running:
                 break
