@@ -349,13 +349,15 @@ def kernels_probe(args):
 
 
 SERVE_CATALOGUE = {
-    # key: (centre cells n, layers nz, degree, core cells), O-grid chamber, 2 face layers
-    "r1-0.27M": (22, 27, 1, (2, 2, 3)),
-    "r1-1.2M": (36, 44, 1, (2, 2, 3)),
+    # key: (centre cells n, layers nz, degree, core cells), O-grid chamber, 2 face layers; the core
+    # cells keep the largest subdomain at 1.9k-4k unknowns (at r = 1, 2x2x3 cells give subdomains
+    # of at most 443 unknowns and one-level ORAS then needs thousands of iterations)
+    "r1-0.27M": (22, 27, 1, (4, 4, 6)),
+    "r1-1.2M": (36, 44, 1, (4, 4, 6)),
     "r2-0.23M": (12, 14, 2, (2, 2, 3)),
-    "r2-1.48M": (22, 27, 2, (2, 2, 3)),
+    "r2-1.48M": (22, 27, 2, (3, 3, 3)),
     "r3-0.21M": (8, 10, 3, (1, 2, 2)),
-    "r3-0.71M": (12, 15, 3, (1, 2, 2)),
+    "r3-0.71M": (12, 15, 3, (2, 2, 2)),
 }
 
 
@@ -400,7 +402,7 @@ def serve_bench(args):
             for j, k in enumerate(keys)]
     Server(backend, budget=budget, slots=4).run(warm, realtime=False)
     def finished(r):   # one line per completed request (the run's progress)
-        state = "failed" if r.error else f"{len(r.sources)} sources, {r.reused}"
+        state = f"failed: {r.error[:300]}" if r.error else f"{len(r.sources)} sources, {r.reused}"
         log(f"[serve] request {r.rid} on {r.mesh} done at {r.finish:.1f}s ({state})")
 
     server = Server(backend, budget=budget, slots=4, on_finish=finished)
@@ -446,8 +448,10 @@ def serve_bench(args):
                    ", ".join(f"{k} ({sizes[k]} unknowns)" for k in keys) +
                    ", a new seeded head per request, 1-32 dipoles per request, mixed precision, block GMRES, "
                    "4 slots, per-subdomain factor residency",
-                   "requests_arrived": len(reqs), "requests_served": len(done), "failed_or_unconverged":
-                   len(reqs) - len(done) + len(bad), "duration_s": args.duration or None,
+                   "requests_arrived": len(reqs), "requests_served": len(done),
+                   "requests_not_started_by_the_end": sum(1 for r in reqs if r.start is None),
+                   "failed_or_unconverged": sum(1 for r in reqs if r.start is not None and r.error) + len(bad),
+                   "duration_s": args.duration or None,
                    "budget_gb": args.budget_gb},
         "latency_s": {"p50": st["p50_s"], "p99": st["p99_s"]},
         "reuse": {"factors_kept_fraction": 1.0 - refac / max(1, total_sub),

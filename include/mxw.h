@@ -305,7 +305,11 @@ mxw_status mxw_problem_rhs_noalloc(mxw_problem* prob, int32_t nrhs, const mxw_so
 mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_dev, double* y_dev,
                                void* stream);
 /* z = M^{-1} v (ORAS: restrict, local LU solves, Boolean prolongation).
- * With nrhs >= 2 (ORAS) every factor strip is read once per 32 columns. */
+ * With nrhs >= 2 (ORAS) every factor strip is read once per 32 columns;
+ * with 16 <= nrhs <= 32 the columns are first copied to a temporary
+ * interleaved layout (ndof x 32 complex128) so that the local solves gather
+ * an unknown's columns in one read.  Temporaries are allocated through the
+ * problem's context. */
 mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double* v_dev, double* z_dev,
                                   void* stream);
 

@@ -2379,6 +2379,7 @@ mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double*
     set_error(tmp.why);
     return MXW_ENOMEM;
   }
+  double2* vil = nullptr;
   if (!gathered(prob->variant) && nrhs >= 2) {
     const int nchunk = (nrhs + multi_chunk_cols() - 1) / multi_chunk_cols();
     xbuf = tmp.alloc<unsigned char>((size_t)nchunk * 2 * prob->L.sum_ns * multi_chunk_cols() * (prob->mixed ? 4 : 8));
@@ -2386,8 +2387,18 @@ mxw_status mxw_problem_apply_prec(mxw_problem* prob, int32_t nrhs, const double*
       set_error(tmp.why);
       return MXW_ENOMEM;
     }
+    // a block of kIlMinCols..32 columns is gathered from an interleaved copy,
+    // as in the block solver
+    if (nrhs >= kIlMinCols && nrhs <= interleaved_cols()) {
+      if (!(vil = tmp.alloc<double2>((size_t)prob->L.ndof * interleaved_cols()))) {
+        set_error(tmp.why);
+        return MXW_ENOMEM;
+      }
+      launch_to_interleaved(st, prob->L.ndof, nrhs, (const double2*)v_dev, prob->L.ndof, vil);
+    }
   }
-  apply_prec_dev(prob, st, (const double2*)v_dev, prob->L.ndof, (double2*)z_dev, prob->L.ndof, nrhs, nullptr, ys, xbuf);
+  apply_prec_dev(prob, st, (const double2*)v_dev, prob->L.ndof, (double2*)z_dev, prob->L.ndof, nrhs, nullptr, ys, xbuf,
+                 vil);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));   // before tmp goes back to the allocator
   return MXW_OK;

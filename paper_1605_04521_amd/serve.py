@@ -122,14 +122,18 @@ class Scheduler:
 class GpuBackend:
     """Resident problems per mesh on one GPU, all allocated through one
     library context whose budget is the loop's (the library refuses what
-    admission would have let through by mistake)."""
+    admission would have let through by mistake), straight from hipMalloc."""
 
     def __init__(self, catalogue, budget: int = 0, slots: int = 4):
         import torch
         from .api import Context, Layout
         self.catalogue = catalogue       # mesh key -> gen.Problem (mesh, partition, k0, degree)
         self.layouts = {k: Layout.from_problem(p) for k, p in catalogue.items()}
-        self.ctx = Context(budget=budget)
+        # hipMalloc / hipFree per allocation: problems of very different sizes
+        # come and go, and memory returned to a caching allocator stays split
+        # among its cached segments (a later large request then fails although
+        # the budget has room)
+        self.ctx = Context(budget=budget, allocator="hip")
         self.idle = []                   # Resident
         self.copies = set()              # meshes whose shared device copy is counted
         self.allocated = 0

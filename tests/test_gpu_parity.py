@@ -189,11 +189,12 @@ def test_pseudo_block_columns_match_single():
 
 
 @pytest.mark.parametrize("precision", [B.MXW_FP64, B.MXW_MIXED])
-@pytest.mark.parametrize("ncol", [5, 33])
+@pytest.mark.parametrize("ncol", [5, 20, 33])
 def test_multi_column_local_solve(precision, ncol):
     """The all-columns ORAS kernel (factor strips read once per 32 columns,
     MFMA products) equals the one-column kernel to rounding, including a ragged
-    column chunk and a second chunk."""
+    column chunk and a second chunk; 20 columns take the gather from the
+    interleaved copy (16..32 columns)."""
     prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2)
     say(f"[gpu] multi-column ORAS precision={precision} ncol={ncol}")
     P = Problem.from_problem(prob, precision=precision)
