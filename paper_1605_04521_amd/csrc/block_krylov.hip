@@ -206,18 +206,18 @@ int bgram_parts(int64_t n, int nchunks) {
 
 // out[b][i] = beta C[b][i] + alpha sum_q A[q][i] M[q][b] for b < p <= 32, q < K;
 // M column-major K x p with leading dimension ldm.  Formed as out^T = M^T A^T:
-// a workgroup covers 128 entries i, each wave 32 b x 32 i (lanes run along i,
-// so the stores of out are coalesced).  Per step of 16 q the workgroup stages
-// the 16 x 128 tile of A (rows of 2 KB, coalesced) and the 16 x p tile of M
-// (read once per workgroup instead of once per wave) in LDS; the next step's
-// tiles are loaded into registers while the current one is multiplied.  out
-// may be C.
-__global__ void __launch_bounds__(256, 2) k_bupdate(const double2* __restrict__ A, int K, const double2* __restrict__ M,
+// a workgroup covers 64 entries i, each wave 32 b x 16 i (lanes run along i,
+// so the stores of out are coalesced); four workgroups per CU.  Per step of
+// 16 q the workgroup stages the 16 x 64 tile of A (rows of 1 KB, coalesced)
+// and the 16 x p tile of M (read once per workgroup instead of once per
+// wave) in LDS; the next step's tiles are loaded into registers while the
+// current one is multiplied.  out may be C.
+__global__ void __launch_bounds__(256, 3) k_bupdate(const double2* __restrict__ A, int K, const double2* __restrict__ M,
                                                  int ldm, int p, int64_t n, double alpha, double beta,
                                                  const double2* C, double2* out, const int* __restrict__ cond) {
   if (cond && !*cond) return;   // a step's optional work, decided on the device
   typedef Mfma<double>::acc_t acc_t;
-  constexpr int KS = 16, IW = 128;
+  constexpr int KS = 16, IW = 64;
   constexpr int LA = KS * IW / 256, LM = KS * kMaxBlockP / 256;
   __shared__ double2 As[KS][IW + 1];
   __shared__ double2 Ms[KS][kMaxBlockP + 1];
@@ -225,11 +225,9 @@ __global__ void __launch_bounds__(256, 2) k_bupdate(const double2* __restrict__ 
   const int64_t i0 = (int64_t)blockIdx.x * IW;
   // m a by three real products (Gauss): P1 = mr ar, P2 = mi ai,
   // P3 = (mr + mi)(ar + ai); Re = P1 - P2, Im = P3 - P1 - P2
-  acc_t p1[2][2], p2[2][2], p3[2][2];
+  acc_t p1[2], p2[2], p3[2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) p1[t][u] = p2[t][u] = p3[t][u] = acc_t{0, 0, 0, 0};
+  for (int t = 0; t < 2; ++t) p1[t] = p2[t] = p3[t] = acc_t{0, 0, 0, 0};
   double2 pa[LA], pm[LM];
   auto fetch = [&](int q0) {
 #pragma unroll
@@ -263,51 +261,40 @@ __global__ void __launch_bounds__(256, 2) k_bupdate(const double2* __restrict__ 
 #pragma unroll
     for (int s4 = 0; s4 < KS / 4; ++s4) {
       const int r = 4 * s4 + lk;
-      double2 m[2], a[2];
-      double ms[2], as[2];
+      const double2 a = As[r][wave * 16 + li];
+      const double as = a.x + a.y;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        m[q] = Ms[r][q * 16 + li];
-        a[q] = As[r][wave * 32 + q * 16 + li];
-        ms[q] = m[q].x + m[q].y;
-        as[q] = a[q].x + a[q].y;
+      for (int t = 0; t < 2; ++t) {
+        const double2 m = Ms[r][t * 16 + li];
+        p1[t] = Mfma<double>::op(m.x, a.x, p1[t]);
+        p2[t] = Mfma<double>::op(m.y, a.y, p2[t]);
+        p3[t] = Mfma<double>::op(m.x + m.y, as, p3[t]);
       }
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          p1[t][u] = Mfma<double>::op(m[t].x, a[u].x, p1[t][u]);
-          p2[t][u] = Mfma<double>::op(m[t].y, a[u].y, p2[t][u]);
-          p3[t][u] = Mfma<double>::op(ms[t], as[u], p3[t][u]);
-        }
     }
     __syncthreads();
   }
-  const int64_t ibase = i0 + wave * 32;
+  const int64_t i = i0 + wave * 16 + li;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int b = t * 16 + Mfma<double>::row(lane, v);
-        const int64_t i = ibase + u * 16 + li;
-        if (b < p && i < n) {
-          const double re = p1[t][u][v] - p2[t][u][v], im = p3[t][u][v] - p1[t][u][v] - p2[t][u][v];
-          double2 r = make_double2(alpha * re, alpha * im);
-          if (beta != 0.0) {
-            const double2 c = C[(int64_t)b * n + i];
-            r.x += beta * c.x;
-            r.y += beta * c.y;
-          }
-          out[(int64_t)b * n + i] = r;
+    for (int v = 0; v < 4; ++v) {
+      const int b = t * 16 + Mfma<double>::row(lane, v);
+      if (b < p && i < n) {
+        const double re = p1[t][v] - p2[t][v], im = p3[t][v] - p1[t][v] - p2[t][v];
+        double2 r = make_double2(alpha * re, alpha * im);
+        if (beta != 0.0) {
+          const double2 c = C[(int64_t)b * n + i];
+          r.x += beta * c.x;
+          r.y += beta * c.y;
         }
+        out[(int64_t)b * n + i] = r;
       }
+    }
 }
 
 void launch_bupdate(hipStream_t st, const double2* A, int K, const double2* M, int ldm, int p, int64_t n,
                     double alpha, double beta, const double2* C, double2* out, const int* cond) {
-  hipLaunchKernelGGL(k_bupdate, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, A, K, M, ldm, p, n, alpha,
+  hipLaunchKernelGGL(k_bupdate, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, A, K, M, ldm, p, n, alpha,
                      beta, C, out, cond);
 }
 
