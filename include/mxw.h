@@ -387,7 +387,8 @@ mxw_status mxw_smatrix(mxw_problem* prob, int32_t nports, const mxw_source* port
  * blocks, Cholesky QR of each new block, block least squares), and the new
  * space is the k harmonic Ritz vectors of the cycle's search space, whose
  * projected matrix has nrhs rows below the Krylov part (restart + nrhs <=
- * 65).  iters_out then counts block steps (the same for every column).
+ * 65; k + nrhs <= restart, so that a cycle holds at least one block step).
+ * iters_out then counts block steps (the same for every column).
  * Other krylov values solve the columns one after another as above.
  * A different k or restart than the previous call drops the space; a
  * different block width keeps it.  Device memory held by the problem:

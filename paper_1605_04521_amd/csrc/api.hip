@@ -2955,8 +2955,9 @@ mxw_status mxw_solve_recycle(mxw_problem* P, int32_t nrhs, const double* b_dev, 
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> hold(P->run);
   if (opts->krylov == MXW_KRYLOV_BLOCK && nrhs >= 2) {
-    if (nrhs > kRecycleMaxBlockP || opts->restart + nrhs > kRecycleLd) {
-      set_error("block recycling takes 2..16 right-hand sides and restart + nrhs <= 65");
+    // a cycle holds C (k vectors) and at least one block step: k + nrhs <= restart
+    if (nrhs > kRecycleMaxBlockP || opts->restart + nrhs > kRecycleLd || k + nrhs > opts->restart) {
+      set_error("block recycling takes 2..16 right-hand sides, k + nrhs <= restart and restart + nrhs <= 65");
       return MXW_EINVAL;
     }
     TRY(ensure_recycle(P, st, k, opts->restart, nrhs));

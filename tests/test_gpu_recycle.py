@@ -187,8 +187,8 @@ def test_recycling_oas_variant(variant):
 def test_recycling_mixed_precision():
     """FP32 local factors (the precision of the batched path) under the FP64
     GCRO-DR: every system of a 1 %-varying sequence reaches the tolerance and
-    the E-field agrees with the FP64 oracle's GCRO-DR to 1e-5 (the mixed
-    path's stated error), with at most 3 more Arnoldi steps."""
+    the E-field agrees with the FP64 oracle's GCRO-DR to 1e-6 (the bar of the
+    mixed end-to-end tests), with at most 3 more Arnoldi steps."""
     base = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1)
     k, m = 8, 20
     say("[gpu] recycling sequence, FP32 local factors")
@@ -207,7 +207,7 @@ def test_recycling_mixed_precision():
         xo, ito, _, ok = gcrodr(lambda v: orc.A @ v, orc.prec.apply, bo, sp, restart=m)
         err = np.linalg.norm(to_np(x)[0] - xo) / np.linalg.norm(xo)
         say(f"   step {step}: iters gpu={it[0]} oracle={ito} relres {rr[0]:.2e} E err {err:.2e}")
-        assert ok and rr[0] <= 1e-8 and err <= 1e-5
+        assert ok and rr[0] <= 1e-8 and err <= 1e-6
         assert int(it[0]) <= ito + 3
 
 
@@ -247,14 +247,15 @@ def test_block_recycling_sequence_matches_oracle(case):
     media differ by 1 % (then 2 %), then a single-source GCRO-DR solve that
     goes on with the same recycled space (a narrower call keeps it), every
     solve against the oracle's with the same space, k and cycle length.
-    FP32 local factors: the mixed path's 1e-5 E-field bar, +-3 steps."""
+    FP32 local factors: E within 1e-6 as well (the outer FP64 iteration
+    reaches the same true residual), +-3 steps."""
     cfg = BLOCK_CASES[case]
     if cfg["kind"] == "chamber":
         base = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1, n_sources=4)
     else:
         base = gen.cube_planewave_problem(n=6, degree=1, box=3, overlap=1, n_sources=4)
     mixed = cfg["precision"] == B.MXW_MIXED
-    etol, itol = (1e-5, 3) if mixed else (1e-6, 1)
+    etol, itol = (1e-6, 3) if mixed else (1e-6, 1)
     k, m, p = 8, 24, 4
     say(f"[gpu] block recycling sequence {case} k={k} m={m} p={p}")
     sp = RecycleSpace(k)
@@ -297,8 +298,9 @@ def test_block_recycling_sequence_matches_oracle(case):
 
 
 def test_block_recycling_options():
-    """Block widths outside 2..16, restart + width above 65 and a zero
-    column are rejected; a width of one with block=True is the one-column
+    """Block widths outside 2..16, restart + width above 65, k + width above
+    restart (no room for a block step in a cycle) and a zero column are
+    rejected; a width of one with block=True is the one-column
     GCRO-DR."""
     prob = gen.chamber_problem(n=4, degree=2, n_sub=6, overlap=1, n_sources=2)
     say("[gpu] block recycling: options")
@@ -308,6 +310,8 @@ def test_block_recycling_options():
         P.solve_recycle(torch.cat([b] * 9), k=4, restart=40, block=True)       # 18 columns
     with pytest.raises(B.MxwError):
         P.solve_recycle(b, k=4, restart=64, block=True)                        # 64 + 2 > 65
+    with pytest.raises(B.MxwError):
+        P.solve_recycle(b, k=19, restart=20, block=True)                       # no room for a block step
     with pytest.raises(B.MxwError):
         P.solve_recycle(torch.stack([b[0], torch.zeros_like(b[0])]), k=4, restart=20, block=True)
     x1, it1, _, _ = P.solve_recycle(b[:1], k=4, restart=20, block=True)
