@@ -301,7 +301,9 @@ mxw_status mxw_problem_rhs(mxw_problem* prob, int32_t nrhs, const mxw_source* sr
  * Synchronises the stream like mxw_problem_rhs. */
 mxw_status mxw_problem_rhs_noalloc(mxw_problem* prob, int32_t nrhs, const mxw_source* src, double* b_dev,
                                    void* stream);
-/* y = A x for nrhs device vectors [nrhs][ndof] complex128. */
+/* y = A x for nrhs device vectors [nrhs][ndof] complex128.  16..32 columns
+ * go through a temporary interleaved copy (ndof x 32 complex128, allocated
+ * through the problem's context): the matrix is read once for all of them. */
 mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_dev, double* y_dev,
                                void* stream);
 /* z = M^{-1} v (ORAS: restrict, local LU solves, Boolean prolongation).

@@ -2355,6 +2355,22 @@ mxw_status mxw_problem_apply_A(mxw_problem* prob, int32_t nrhs, const double* x_
     return MXW_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
+  if (nrhs >= kIlMinCols && nrhs <= interleaved_cols()) {
+    // a block of columns as in the block solver: the matrix read once for
+    // all of them, through a temporary interleaved copy
+    DevMem tmp(prob->ctx, st);
+    double2* xi = tmp.alloc<double2>((size_t)prob->L.ndof * interleaved_cols());
+    if (!xi) {
+      set_error(tmp.why);
+      return MXW_ENOMEM;
+    }
+    ScopedKernelTimer tm("spmv");
+    launch_spmm_interleaved(st, prob->L.ndof, nrhs, prob->rowptr, prob->cols, prob->vals, (const double2*)x_dev,
+                            prob->L.ndof, xi, (double2*)y_dev, prob->L.ndof, nullptr, 0);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));   // before tmp goes back to the allocator
+    return MXW_OK;
+  }
   spmv_dev(prob, st, (const double2*)x_dev, (double2*)y_dev, nullptr, nrhs, nullptr);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));

@@ -354,7 +354,8 @@ def test_block_graph_replay_matches_eager(nsrc):
 def test_multi_column_spmv():
     """The fused several-column product (matrix read once per 8 columns) equals
     the one-column product on each column, including a ragged last group and
-    inactive columns left untouched."""
+    inactive columns left untouched; so does the interleaved product of a block
+    of 16..32 columns."""
     prob = gen.chamber_problem(n=6, degree=2, n_sub=9, overlap=2)
     say("[gpu] multi-column SpMV vs one column")
     P = Problem.from_problem(prob, defer_factor=True)
@@ -365,6 +366,14 @@ def test_multi_column_spmv():
     for c in range(11):
         y1 = to_np(P.apply_A(Xt[c:c + 1]))[0]
         assert np.linalg.norm(Y[c] - y1) <= 1e-15 * np.linalg.norm(y1), c
+    # 20 columns: the interleaved product (each row's entries summed in row
+    # order, a different order from the one-column kernel)
+    X2 = rng.standard_normal((20, P.ndof)) + 1j * rng.standard_normal((20, P.ndof))
+    X2t = torch.from_numpy(X2).cuda()
+    Y2 = to_np(P.apply_A(X2t))
+    for c in range(20):
+        y1 = to_np(P.apply_A(X2t[c:c + 1]))[0]
+        assert np.linalg.norm(Y2[c] - y1) <= 1e-14 * np.linalg.norm(y1), c
 
 
 @pytest.mark.parametrize("restart", [50, 4])
