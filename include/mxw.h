@@ -359,9 +359,11 @@ mxw_status mxw_problem_device_bytes(const mxw_problem* prob, uint64_t* bytes);
  * nports ports (MXW_SRC_PORT sources): S_ij = int_{Gamma_i} conj(E_j) . E0_i
  * / int_{Gamma_i} |E0_i|^2, the integrals taken with the right-hand sides'
  * face quadrature; S_dev receives device complex128 [nports][nsol]
- * (caller-allocated).  Allocates temporary device buffers and synchronises
- * the stream.  MXW_EINVAL for a source that is not a valid port or a port
- * with no face. */
+ * (caller-allocated).  The fields follow the exp(-i omega t) convention of
+ * the library (Im eps > 0 lossy), so S is the complex conjugate of eq. (5)'s
+ * S in an exp(+i omega t) convention.  Allocates temporary device buffers
+ * and synchronises the stream.  MXW_EINVAL for a source that is not a valid
+ * port or a port with no face. */
 mxw_status mxw_smatrix(mxw_problem* prob, int32_t nports, const mxw_source* ports, int32_t nsol,
                        const double* X_dev, void* stream, double* S_dev);
 
