@@ -29,6 +29,7 @@
 namespace mxw {
 
 constexpr int kPad = 4;
+constexpr int kSub = 8;   // columns of a sub-panel (delayed updates of the panel's later columns)
 
 template <typename R, int NB>
 struct PanelSmem {
@@ -324,6 +325,12 @@ __device__ __forceinline__ void lu_subdomain(int s, LuSmem<R, NB>& smu, R* __res
     }
     for (int jj = 0; jj < kb; ++jj) {
       const int j = k + jj;
+      // FP32: sub-panel [s0, s_end) of kSub columns: its own columns are
+      // updated at every step, the panel's columns right of it once, when it
+      // is done.  FP64 updates the whole panel at every step (the delayed
+      // update's registers would spill)
+      constexpr int kS = sizeof(R) == 4 ? kSub : NB;
+      const int s0 = jj / kS * kS, s_end = min(s0 + kS, kb);
       wave_argmax(best, bi);
       if (lane == 0) {
         sm.rv[wave] = best;
@@ -360,10 +367,10 @@ __device__ __forceinline__ void lu_subdomain(int s, LuSmem<R, NB>& smu, R* __res
       const R rr = den > R(0) ? pr / den : R(0), ri = den > R(0) ? -pi / den : R(0);
       best = -1.0;
       bi = 0x7fffffff;
-      // scale column j and update the columns right of it, one row per
-      // thread at a time: the row's entries of 16 columns are loaded together
-      // (branch-free buffer accesses, masked columns out of range), updated
-      // in registers and stored
+      // scale column j and update the sub-panel's columns right of it, one
+      // row per thread at a time: the row's entries of 16 columns are loaded
+      // together (branch-free buffer accesses, masked columns out of range),
+      // updated in registers and stored
       for (int i = j + 1 + tid; i < n; i += 512) {
         int row[2] = {i, i + 256};
         int oj[2];
@@ -379,7 +386,7 @@ __device__ __forceinline__ void lu_subdomain(int s, LuSmem<R, NB>& smu, R* __res
         }
 #pragma nounroll
         for (int h = 0; h < NB; h += HC) {
-          if (h + HC <= jj + 1 || h >= kb) continue;   // uniform: no live column in this part
+          if (h + HC <= jj + 1 || h >= s_end) continue;   // uniform: no live column in this part
           R xr[2][HC], xi[2][HC];
           int off[2][HC];
 #pragma unroll
@@ -387,7 +394,7 @@ __device__ __forceinline__ void lu_subdomain(int s, LuSmem<R, NB>& smu, R* __res
 #pragma unroll
             for (int u = 0; u < HC; ++u) {
               const int c = h + u;
-              off[t][u] = (c > jj && c < kb && row[t] < n) ? ((k + c) * (int)ld + row[t]) * (int)sizeof(R) : kOob;
+              off[t][u] = (c > jj && c < s_end && row[t] < n) ? ((k + c) * (int)ld + row[t]) * (int)sizeof(R) : kOob;
               xr[t][u] = BufLoad<R>::at(fr, off[t][u]);
               xi[t][u] = BufLoad<R>::at(fi, off[t][u]);
             }
@@ -408,6 +415,80 @@ __device__ __forceinline__ void lu_subdomain(int s, LuSmem<R, NB>& smu, R* __res
               BufStore<R>::at(fr, off[t][u], xr[t][u]);
               BufStore<R>::at(fi, off[t][u], xi[t][u]);
             }
+        }
+      }
+      if (sizeof(R) == 4 && jj + 1 == s_end && s_end < kb) {
+        // the sub-panel is factorised: U12 = L11^{-1} A12 on its pivot rows
+        // (one thread per later column), then A22 -= L21 U12 on the rows
+        // below it, which also yields the next column's pivot candidates
+        const int ns = s_end - s0, nc = kb - s_end;
+        __syncthreads();
+        if (tid < nc) {
+          const int c = s_end + tid;
+          R ur[kSub], ui[kSub];
+#pragma unroll
+          for (int i = 0; i < kSub; ++i) {
+            if (i >= ns) break;
+            const int64_t o = (int64_t)(k + c) * ld + k + s0 + i;
+            R xr = Ar[o], xi = Ai[o];
+#pragma unroll
+            for (int m = 0; m < kSub; ++m) {
+              if (m >= i) break;
+              const int64_t ol = (int64_t)(k + s0 + m) * ld + k + s0 + i;   // L[s0 + i][s0 + m]
+              const R lr = Ar[ol], li = Ai[ol];
+              xr -= lr * ur[m] - li * ui[m];
+              xi -= lr * ui[m] + li * ur[m];
+            }
+            ur[i] = xr;
+            ui[i] = xi;
+            Ar[o] = xr;
+            Ai[o] = xi;
+            sm.Bre[i][c] = xr;
+            sm.Bim[i][c] = xi;
+          }
+        }
+        __syncthreads();
+        for (int r = k + s_end + tid; r < n; r += 256) {
+          R lr[kSub], li[kSub];
+#pragma unroll
+          for (int m = 0; m < kSub; ++m) {
+            const int o = m < ns ? ((k + s0 + m) * (int)ld + r) * (int)sizeof(R) : kOob;
+            lr[m] = BufLoad<R>::at(fr, o);
+            li[m] = BufLoad<R>::at(fi, o);
+          }
+#pragma nounroll
+          for (int c0 = s_end; c0 < kb; c0 += 4) {
+            R xr[4], xi[4];
+            int off[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int c = c0 + u;
+              off[u] = c < kb ? ((k + c) * (int)ld + r) * (int)sizeof(R) : kOob;
+              xr[u] = BufLoad<R>::at(fr, off[u]);
+              xi[u] = BufLoad<R>::at(fi, off[u]);
+            }
+#pragma unroll
+            for (int m = 0; m < kSub; ++m)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u;
+                const R ur = (m < ns && c < kb) ? sm.Bre[m][c] : R(0), ui = (m < ns && c < kb) ? sm.Bim[m][c] : R(0);
+                xr[u] -= lr[m] * ur - li[m] * ui;
+                xi[u] -= lr[m] * ui + li[m] * ur;
+              }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (c0 + u == s_end) {
+                const double v = fabs((double)xr[u]) + fabs((double)xi[u]);
+                if (v > best || (v == best && r < bi)) {
+                  best = v;
+                  bi = r;
+                }
+              }
+              BufStore<R>::at(fr, off[u], xr[u]);
+              BufStore<R>::at(fi, off[u], xi[u]);
+            }
+          }
         }
       }
     }
