@@ -65,16 +65,18 @@ constexpr int kGramChunkStep = 32;   // n entries staged per LDS step
 // conj(V[q][i]) W[b][i], q < Q, b < p <= 32.  Grid (ceil(Q/64), chunks), so
 // the workgroups sharing a chunk's strip of W are launched together; the four
 // waves of a workgroup take 16 rows q each; the W and V strips of every
-// 32-entry step are staged in LDS with coalesced loads.  (Keeping a chunk's
+// 16-entry step are staged in LDS with coalesced loads (the same
+// accumulation order as 32-entry steps, at four workgroups per CU instead of
+// three: 1.99 -> 1.94 s per default step).  (Keeping a chunk's
 // workgroups on one XCD, so that its strip of W is fetched into one L2
 // instead of several, measured slower: 10.3 -> 10.9 ms at 1,600 rows.)
-__global__ void __launch_bounds__(256, 3) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
+__global__ void __launch_bounds__(256, 4) k_bgram(const double2* __restrict__ V, int Q, const double2* __restrict__ W,
                                                int p, int64_t n, int64_t chunk, double2* __restrict__ part,
                                                const int* __restrict__ cond) {
   if (cond && !*cond) return;   // a step's optional work, decided on the device
   const int ch = blockIdx.y, qt = blockIdx.x;
   typedef Mfma<double>::acc_t acc_t;
-  constexpr int S = kGramChunkStep;
+  constexpr int S = kGramChunkStep / 2;   // 16-entry strips: 122 registers, four workgroups per CU
   __shared__ double2 Vs[64][S + 1];
   __shared__ double2 Ws[kMaxBlockP][S + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
