@@ -334,9 +334,68 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
 // column over the row's entries in order (a different summation order from
 // k_spmv).  The 32 x 32 result tile of a block goes through LDS so that the
 // column-major output is written in 512-byte runs.
+//
+// The unknowns of one mesh entity share their row pattern (the degree-r
+// Nedelec basis places several unknowns on each edge and face), so rows 2g
+// and 2g+1 usually have the same columns.  A half-wave takes such a pair
+// together: it checks the pattern with one ballot, then gathers each x row
+// once for both rows (half the gathers, which bound this kernel), keeping
+// each row's own summation order.  Pairs whose patterns differ are summed
+// row by row.
 constexpr int kIlCols = 32;
 constexpr int kIlRows = 32;   // rows per workgroup
-__global__ void __launch_bounds__(256) k_spmm_il(int64_t n, int p, const int64_t* __restrict__ rowptr,
+
+__device__ inline void il_accumulate(const double2 a, const double2 xv, double& sr, double& si) {
+  sr += a.x * xv.x - a.y * xv.y;
+  si += a.x * xv.y + a.y * xv.x;
+}
+
+// one row, entries [r0, r1), this lane's column
+__device__ inline void il_row(int64_t r0, int64_t r1, const int* __restrict__ cols,
+                              const double2* __restrict__ vals, const double2* __restrict__ xi, int lane, double& sr,
+                              double& si) {
+  for (int64_t e = r0; e < r1; e += 4) {
+    int ci[4];
+    double2 a[4], xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = e + u < r1;
+      ci[u] = ok ? cols[e + u] : 0;
+      a[u] = ok ? vals[e + u] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = xi[(int64_t)ci[u] * kIlCols + lane];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) il_accumulate(a[u], xv[u], sr, si);
+  }
+}
+
+// two rows with the same columns: entries [a0, a0 + len) and [b0, b0 + len)
+constexpr int kPairUnroll = 4;
+__device__ inline void il_row_pair(int64_t a0, int64_t b0, int64_t len, const int* __restrict__ cols,
+                                   const double2* __restrict__ vals, const double2* __restrict__ xi, int lane,
+                                   double& ar, double& ai, double& br, double& bi) {
+  for (int64_t e = 0; e < len; e += kPairUnroll) {
+    int ci[kPairUnroll];
+    double2 a[kPairUnroll], b[kPairUnroll], xv[kPairUnroll];
+#pragma unroll
+    for (int u = 0; u < kPairUnroll; ++u) {
+      const bool ok = e + u < len;
+      ci[u] = ok ? cols[a0 + e + u] : 0;
+      a[u] = ok ? vals[a0 + e + u] : make_double2(0.0, 0.0);
+      b[u] = ok ? vals[b0 + e + u] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPairUnroll; ++u) xv[u] = xi[(int64_t)ci[u] * kIlCols + lane];
+#pragma unroll
+    for (int u = 0; u < kPairUnroll; ++u) {
+      il_accumulate(a[u], xv[u], ar, ai);
+      il_accumulate(b[u], xv[u], br, bi);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256, 6) k_spmm_il(int64_t n, int p, const int64_t* __restrict__ rowptr,
                                                  const int* __restrict__ cols, const double2* __restrict__ vals,
                                                  const double2* __restrict__ xi, double2* __restrict__ y,
                                                  int64_t ystride, const double2* __restrict__ b, int64_t bstride) {
@@ -344,30 +403,28 @@ __global__ void __launch_bounds__(256) k_spmm_il(int64_t n, int p, const int64_t
   const int lane = threadIdx.x & 31;
   const int sub = threadIdx.x >> 5;   // 8 half-waves
   const int64_t row0 = (int64_t)blockIdx.x * kIlRows;
-  for (int rr = sub; rr < kIlRows; rr += 8) {
-    const int64_t row = row0 + rr;
-    double sr = 0.0, si = 0.0;
-    if (row < n) {
-      const int64_t r0 = rowptr[row], r1 = rowptr[row + 1];
-      for (int64_t e = r0; e < r1; e += 4) {
-        int ci[4];
-        double2 a[4], xv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const bool ok = e + u < r1;
-          ci[u] = ok ? cols[e + u] : 0;
-          a[u] = ok ? vals[e + u] : make_double2(0.0, 0.0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = xi[(int64_t)ci[u] * kIlCols + lane];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          sr += a[u].x * xv[u].x - a[u].y * xv[u].y;
-          si += a[u].x * xv[u].y + a[u].y * xv[u].x;
-        }
+  for (int k = sub; k < kIlRows / 2; k += 8) {
+    const int64_t ra = row0 + 2 * k, rb = ra + 1;
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    if (ra < n) {
+      const int64_t a0 = rowptr[ra], a1 = rowptr[ra + 1];
+      const int64_t b1 = rb < n ? rowptr[rb + 1] : a1;
+      bool paired = rb < n && b1 - a1 == a1 - a0;
+      if (paired) {
+        bool same = true;
+        for (int64_t e = lane; e < a1 - a0; e += 32) same = same && cols[a0 + e] == cols[a1 + e];
+        const unsigned long long miss = __ballot(!same);
+        paired = ((miss >> (threadIdx.x & 32)) & 0xffffffffull) == 0;
+      }
+      if (paired) {
+        il_row_pair(a0, a1, a1 - a0, cols, vals, xi, lane, ar, ai, br, bi);
+      } else {
+        il_row(a0, a1, cols, vals, xi, lane, ar, ai);
+        if (rb < n) il_row(a1, b1, cols, vals, xi, lane, br, bi);
       }
     }
-    tile[rr][lane] = make_double2(sr, si);
+    tile[2 * k][lane] = make_double2(ar, ai);
+    tile[2 * k + 1][lane] = make_double2(br, bi);
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < kIlRows * kIlCols; idx += 256) {

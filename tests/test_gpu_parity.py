@@ -77,6 +77,15 @@ def test_matrix_and_rhs(name):
     for c in range(3):
         yo = orc.A @ X[c]
         assert np.linalg.norm(Y[c] - yo) <= 1e-13 * np.linalg.norm(yo)
+    # blocks of 32 and 17 columns take the interleaved product, which sums
+    # row pairs with one column pattern together: these meshes hold no such
+    # pair (r=1), only such pairs (r=2), both kinds and an odd row count (r=3)
+    for ncol in (32, 17):
+        X = rng.standard_normal((ncol, orc.ndof)) + 1j * rng.standard_normal((ncol, orc.ndof))
+        Y = to_np(P.apply_A(torch.from_numpy(X).cuda()))
+        for c in range(ncol):
+            yo = orc.A @ X[c]
+            assert np.linalg.norm(Y[c] - yo) <= 1e-13 * np.linalg.norm(yo), (ncol, c)
 
 
 @pytest.mark.parametrize("name", ["cube8_r1", "cube4_r2", "chamber6_r2", "chamber5_r3"])
