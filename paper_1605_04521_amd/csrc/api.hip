@@ -2030,7 +2030,12 @@ mxw_status recycle_solve_block(mxw_problem* P, hipStream_t st, int p, const doub
       w.history.push_back(worst);
       if (below(est) || bad || steps >= opts->max_iters) break;
     }
-    if (bad) break;
+    if (bad) {   // report the true residual of the iterate reached so far
+      launch_spmv(st, P->spmv_group, n, P->rowptr, P->cols, P->vals, X, n, w.R, n, B, n, p, nullptr);
+      HIP_CHECK(hipGetLastError());
+      TRY(norms(w.R, rn));
+      break;
+    }
     // X += Z Y - Ubar (B Y)
     const int q = jd * p;
     launch_bls_solve(st, q, p, mb, b.Rls, b.E, b.Y);
