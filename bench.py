@@ -27,6 +27,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import atexit
 import hashlib
 import json
 import math
@@ -158,10 +159,15 @@ def cpu_baseline_worker(args):
     application + product with A + orthogonalisation), with the block step
     count the GPU run reports."""
     import multiprocessing as mp
+    import signal
     from oracle.assemble import Discretization
     from oracle.schwarz import owners
     from paper_1605_04521_amd import gen
 
+    # stopped by the benchmark (SIGTERM): leave through the normal exit path,
+    # whose pool cleanup also ends the pool's workers (they keep the default
+    # action, set by the pool's initializer)
+    signal.signal(signal.SIGTERM, lambda *_: sys.exit(1))
     nsub = tuple(int(q) for q in args.nsub.split("x")) if "x" in args.nsub else int(args.nsub)
     prob = gen.chamber_problem(n=args.n, nz=args.nz, degree=args.degree, n_sub=nsub, overlap=args.overlap,
                                seed=args.seed, n_sources=max(args.nrhs, 1))
@@ -181,7 +187,7 @@ def cpu_baseline_worker(args):
     rows = min(d.ndof // workers, 100000)
     bounds = np.linspace(0, d.ndof, workers + 1).astype(np.int64)
     ctx = mp.get_context("fork")
-    with ctx.Pool(workers) as pool:
+    with ctx.Pool(workers, initializer=signal.signal, initargs=(signal.SIGTERM, signal.SIG_DFL)) as pool:
         t0 = time.perf_counter()
         pool.map(_oracle_rows_job, [("spmm", int(bounds[w]), int(bounds[w + 1]), 0) for w in range(workers)],
                  chunksize=1)
@@ -214,6 +220,19 @@ def start_cpu_baseline(args):
     env = dict(os.environ, HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="", OMP_NUM_THREADS="1",
                OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+
+
+def stop_child(proc):
+    """Ends the oracle's timing child if it still runs: SIGTERM first (the
+    child then leaves through its process pool's cleanup), SIGKILL after 10 s."""
+    import subprocess
+    if proc.poll() is None:
+        proc.terminate()
+        try:
+            proc.communicate(timeout=10)
+        except subprocess.TimeoutExpired:
+            proc.kill()
+            proc.communicate()
 
 
 def finish_cpu_baseline(proc, steps, timeout):
@@ -567,6 +586,10 @@ def main():
     cpu_proc = None
     if args.workload == "chamber" and not args.no_cpu_baseline:
         cpu_proc = start_cpu_baseline(args)
+        log(f"[bench] oracle timing started in process {cpu_proc.pid}")
+        # whatever ends this process (no GPU, an error) also ends the child;
+        # after a normal run it has already been collected
+        atexit.register(stop_child, cpu_proc)
 
     import torch
     from paper_1605_04521_amd import _lib as B
